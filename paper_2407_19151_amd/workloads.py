@@ -1,0 +1,305 @@
+"""Seeded synthetic plasmas shaped like the paper's test problems.
+
+This module only draws inputs (velocities, weights, per-cell counts).  It
+holds none of the collision method's arithmetic, so both the GPU path and
+the CPU oracle can be fed from it.
+
+Units are normalized: eps0 = 1, electron mass 1, electron charge magnitude 1,
+cell volume 1.  Relative weights are scaled by one common factor per workload
+so that the mean electron density per cell is 1 (weight ratios unchanged).
+The time step is a fraction of the electron collision time
+
+    tau_e = 3 (2 pi)^{3/2} eps0^2 sqrt(m_e) T_e^{3/2} / (Z n_e e^4 lnL),
+
+the Braginskii form of the paper's tau_e used with the 0D Spitzer model of
+Sec. 5.3 (there in practical units).
+
+Workloads (one particle array per workload, grouped by (cell, species)):
+  1  one electron species, 16 cells x 200, anisotropic Maxwellian
+     (T_x = T_y = 1, T_z = 2), lognormal(0, 1) weights, N97, lnL = 10,
+     dt = 0.05 tau_e(T = 1).
+  2  electrons + ions (m_i = 100, q = +1), 4096 cells, Poisson(256) particles
+     per species per cell, T_e = 2, T_i = 1, w_e = 1, w_i = 10^U(1,2),
+     lnL = 10, dt = 0.05 tau_e(T_e = 2).
+  3  as 2, 65536 cells, N_cell = clip(round(lognormal(ln 200, 1)), 16, 4096)
+     split ceil(N/2) electrons / floor(N/2) ions.
+  4  relativistic beam-plasma, c = 1: 448 background electrons
+     (Maxwell-Juettner, T = 0.05 m c^2), 128 beam electrons (gamma = 3 along
+     x, same thermal spread, weight 1e-2 relative), 448 ions (m = 1836,
+     T_i = T_e, neutralizing weight), 16384 cells, dt = 0.05 tau_e(bg).
+  5  as 2 with 1024 cells x (256 e + 256 i), v0 = sqrt(T0/m) xi.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+TA77 = 0
+N97 = 1
+
+PHILOX_SEED_BASE = 0x2407_1915_1000_0000
+
+
+def tau_e(T: float, n_e: float = 1.0, lnL: float = 10.0, Z: float = 1.0,
+          eps0: float = 1.0, m_e: float = 1.0, e: float = 1.0) -> float:
+    """Electron collision time in the normalized units of this module."""
+    return (3.0 * (2.0 * math.pi) ** 1.5 * eps0 ** 2 * math.sqrt(m_e) * T ** 1.5
+            / (Z * n_e * e ** 4 * lnL))
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    n_cells: int
+    n_species: int
+    offsets: np.ndarray          # int64 [n_cells*n_species + 1]
+    cells: np.ndarray            # int32 [n]
+    species: np.ndarray          # int32 [n]
+    w: np.ndarray                # float64 [n]
+    vx: np.ndarray               # float64 [n] (proper velocity if relativistic)
+    vy: np.ndarray
+    vz: np.ndarray
+    mass: np.ndarray             # float64 [n_species]
+    charge: np.ndarray           # float64 [n_species]
+    collisions: List[Tuple[int, int]]
+    dt: float
+    coulomb_log: float
+    method: int
+    relativistic: bool = False
+    c: float = math.inf
+    eps0: float = 1.0
+    cell_volume: float = 1.0
+    seed: int = PHILOX_SEED_BASE
+    steps: int = 1
+    f_E: float = 0.05
+    extra: Optional[dict] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.w.shape[0])
+
+    def copy(self) -> "Workload":
+        d = dataclasses.replace(self)
+        for k in ("offsets", "cells", "species", "w", "vx", "vy", "vz", "mass", "charge"):
+            setattr(d, k, getattr(self, k).copy())
+        return d
+
+    def velocities(self) -> np.ndarray:
+        return np.stack([self.vx, self.vy, self.vz])
+
+    def particle_collisions_per_step(self) -> int:
+        """Particle-collisions per step: each particle counts once for every
+        collision in the list that includes its species (and that has pairs
+        in its cell)."""
+        cnt = np.diff(self.offsets).reshape(self.n_cells, self.n_species)
+        tot = 0
+        for a, b in self.collisions:
+            if a == b:
+                na = cnt[:, a]
+                tot += int(na[na >= 2].sum())
+            else:
+                na, nb = cnt[:, a], cnt[:, b]
+                ok = (na > 0) & (nb > 0)
+                tot += int(na[ok].sum() + nb[ok].sum())
+        return tot
+
+    def unsorted(self, seed: int = 12345) -> "Workload":
+        """Same particles in a random order (for the unsorted entry point)."""
+        rng = np.random.Generator(np.random.PCG64(seed))
+        perm = rng.permutation(self.n)
+        d = self.copy()
+        for k in ("cells", "species", "w", "vx", "vy", "vz"):
+            setattr(d, k, getattr(self, k)[perm].copy())
+        d.extra = dict(self.extra or {}, perm=perm)
+        return d
+
+
+def _assemble(name, counts, mass, charge, draw, collisions, dt, lnL, method,
+              seed_data, **kw) -> Workload:
+    """counts: int [n_cells, S]; draw(rng, s, n) -> (w_rel, vx, vy, vz)."""
+    rng = np.random.Generator(np.random.PCG64(seed_data))
+    n_cells, S = counts.shape
+    flat = counts.reshape(-1).astype(np.int64)
+    offsets = np.zeros(flat.size + 1, dtype=np.int64)
+    np.cumsum(flat, out=offsets[1:])
+    n = int(offsets[-1])
+    cells = np.repeat(np.repeat(np.arange(n_cells, dtype=np.int32), S), flat)
+    species = np.repeat(np.tile(np.arange(S, dtype=np.int32), n_cells), flat)
+    w = np.empty(n)
+    vx = np.empty(n)
+    vy = np.empty(n)
+    vz = np.empty(n)
+    for s in range(S):
+        idx = np.nonzero(species == s)[0]
+        ws, x, y, z = draw(rng, s, idx.size)
+        w[idx], vx[idx], vy[idx], vz[idx] = ws, x, y, z
+    return Workload(name=name, n_cells=n_cells, n_species=S, offsets=offsets,
+                    cells=cells, species=species, w=w, vx=vx, vy=vy, vz=vz,
+                    mass=np.asarray(mass, dtype=np.float64),
+                    charge=np.asarray(charge, dtype=np.float64),
+                    collisions=list(collisions), dt=dt, coulomb_log=lnL,
+                    method=method, **kw)
+
+
+def _scale_electron_density(wl: Workload, electron_species=(0,)) -> Workload:
+    """Common weight factor so that the mean electron density per cell is 1."""
+    tot = sum(wl.w[wl.species == s].sum() for s in electron_species)
+    scale = wl.n_cells * wl.cell_volume / tot
+    wl.w *= scale
+    wl.extra = dict(wl.extra or {}, weight_scale=scale)
+    return wl
+
+
+def config1(n_cells: int = 16, ppc: int = 200, seed_data: int = 1,
+            method: int = N97) -> Workload:
+    counts = np.full((n_cells, 1), ppc, dtype=np.int64)
+
+    def draw(rng, s, n):
+        w = rng.lognormal(0.0, 1.0, n)
+        return (w, rng.normal(0, 1.0, n), rng.normal(0, 1.0, n),
+                rng.normal(0, math.sqrt(2.0), n))
+
+    wl = _assemble("1: one species, anisotropic Maxwellian, lognormal weights",
+                   counts, [1.0], [-1.0], draw, [(0, 0)],
+                   dt=0.05 * tau_e(1.0), lnL=10.0, method=method,
+                   seed_data=seed_data, seed=PHILOX_SEED_BASE + 1, steps=100)
+    return _scale_electron_density(wl)
+
+
+def _two_species_draw(Te=2.0, Ti=1.0, mi=100.0):
+    def draw(rng, s, n):
+        if s == 0:
+            w = np.ones(n)
+            sig = math.sqrt(Te / 1.0)
+        else:
+            w = 10.0 ** rng.uniform(1.0, 2.0, n)
+            sig = math.sqrt(Ti / mi)
+        return w, rng.normal(0, sig, n), rng.normal(0, sig, n), rng.normal(0, sig, n)
+    return draw
+
+
+def config2(n_cells: int = 4096, mean_ppc: float = 256.0, seed_data: int = 2,
+            method: int = N97) -> Workload:
+    rng = np.random.Generator(np.random.PCG64(seed_data + 1000))
+    counts = rng.poisson(mean_ppc, size=(n_cells, 2)).astype(np.int64)
+    wl = _assemble("2: electrons + ions (m_i = 100), Poisson(256) per species",
+                   counts, [1.0, 100.0], [-1.0, 1.0], _two_species_draw(),
+                   [(0, 0), (1, 1), (0, 1)], dt=0.05 * tau_e(2.0), lnL=10.0,
+                   method=method, seed_data=seed_data,
+                   seed=PHILOX_SEED_BASE + 2, steps=200)
+    return _scale_electron_density(wl)
+
+
+def config3_counts(n_cells: int = 65536, seed_data: int = 3) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(seed_data + 1000))
+    ncell = np.clip(np.rint(rng.lognormal(math.log(200.0), 1.0, n_cells)), 16, 4096)
+    ncell = ncell.astype(np.int64)
+    return np.stack([(ncell + 1) // 2, ncell // 2], axis=1)
+
+
+def config3(n_cells: int = 65536, seed_data: int = 3, method: int = N97) -> Workload:
+    counts = config3_counts(n_cells, seed_data)
+    wl = _assemble("3: 65536 uneven cells, lognormal counts clipped to [16, 4096]",
+                   counts, [1.0, 100.0], [-1.0, 1.0], _two_species_draw(),
+                   [(0, 0), (1, 1), (0, 1)], dt=0.05 * tau_e(2.0), lnL=10.0,
+                   method=method, seed_data=seed_data,
+                   seed=PHILOX_SEED_BASE + 3, steps=20)
+    return _scale_electron_density(wl)
+
+
+def maxwell_juttner_speed(rng, theta: float, n: int) -> np.ndarray:
+    """|u|/c of a Maxwell-Juettner distribution f(u) ~ u^2 exp(-gamma/theta),
+    by inverse CDF on a fine grid."""
+    umax = max(40.0 * math.sqrt(theta), 40.0 * theta + 1.0)
+    grid = np.linspace(0.0, umax, 200001)
+    gam = np.sqrt(1.0 + grid ** 2)
+    pdf = grid ** 2 * np.exp(-(gam - 1.0) / theta)
+    cdf = np.concatenate([[0.0], np.cumsum(0.5 * (pdf[1:] + pdf[:-1]) * np.diff(grid))])
+    cdf /= cdf[-1]
+    return np.interp(rng.uniform(0.0, 1.0, n), cdf, grid)
+
+
+def _iso(rng, speed):
+    n = speed.size
+    mu = rng.uniform(-1.0, 1.0, n)
+    ph = rng.uniform(0.0, 2.0 * math.pi, n)
+    st = np.sqrt(1.0 - mu * mu)
+    return speed * st * np.cos(ph), speed * st * np.sin(ph), speed * mu
+
+
+def config4(n_cells: int = 16384, n_bg: int = 448, n_beam: int = 128,
+            n_ion: int = 448, seed_data: int = 4, method: int = N97) -> Workload:
+    theta = 0.05
+    gb = 3.0
+    mi = 1836.0
+    counts = np.tile(np.array([[n_bg + n_beam, n_ion]], dtype=np.int64), (n_cells, 1))
+    w_ion = 1.0 + 0.01 * n_beam / n_ion
+
+    def draw(rng, s, n):
+        if s == 0:
+            per = n_bg + n_beam
+            u = maxwell_juttner_speed(rng, theta, n)
+            ux, uy, uz = _iso(rng, u)
+            k = np.arange(n) % per
+            beam = k >= n_bg
+            w = np.where(beam, 1e-2, 1.0)
+            # boost the beam particles' thermal proper velocity by gamma = 3 along x
+            bb = math.sqrt(1.0 - 1.0 / gb ** 2)
+            g = np.sqrt(1.0 + ux * ux + uy * uy + uz * uz)
+            ux = np.where(beam, gb * (ux + bb * g), ux)
+            return w, ux, uy, uz
+        u = maxwell_juttner_speed(rng, theta / mi, n)
+        ux, uy, uz = _iso(rng, u)
+        return np.full(n, w_ion), ux, uy, uz
+
+    wl = _assemble("4: relativistic beam through Maxwell-Juettner e-i background",
+                   counts, [1.0, mi], [-1.0, 1.0], draw,
+                   [(0, 0), (1, 1), (0, 1)], dt=0.05 * tau_e(theta), lnL=10.0,
+                   method=method, seed_data=seed_data,
+                   seed=PHILOX_SEED_BASE + 4, steps=500, relativistic=True, c=1.0)
+    # mean background-electron density 1 per cell
+    scale = 1.0 / n_bg
+    wl.w *= scale
+    wl.extra = dict(weight_scale=scale)
+    return wl
+
+
+def config5(n_cells: int = 1024, ppc: int = 256, Te0: float = 2.0, Ti0: float = 1.0,
+            seed_data: int = 5, method: int = N97) -> Workload:
+    counts = np.full((n_cells, 2), ppc, dtype=np.int64)
+    wl = _assemble("5: differentiated relaxation, 1024 cells x (256 e + 256 i)",
+                   counts, [1.0, 100.0], [-1.0, 1.0],
+                   _two_species_draw(Te0, Ti0), [(0, 0), (1, 1), (0, 1)],
+                   dt=0.05 * tau_e(2.0), lnL=10.0, method=method,
+                   seed_data=seed_data, seed=PHILOX_SEED_BASE + 5, steps=50)
+    return _scale_electron_density(wl)
+
+
+def standard_normal_state(wl: Workload, seed_data: int) -> np.ndarray:
+    """Fixed xi ~ N(0,1)^{3 x n} for the reparameterized initial state
+    v0 = sqrt(T0/m) xi of the differentiated relaxation."""
+    rng = np.random.Generator(np.random.PCG64(seed_data + 777))
+    return rng.normal(0.0, 1.0, size=(3, wl.n))
+
+
+def make(config: int, **kw) -> Workload:
+    return {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}[config](**kw)
+
+
+def temperature(wl: Workload, species: int, vx=None, vy=None, vz=None) -> np.ndarray:
+    """Weighted per-species temperature components (T_x, T_y, T_z) about the
+    species' weighted mean velocity (diagnostic)."""
+    vx = wl.vx if vx is None else vx
+    vy = wl.vy if vy is None else vy
+    vz = wl.vz if vz is None else vz
+    sel = wl.species == species
+    w = wl.w[sel]
+    m = wl.mass[species]
+    out = []
+    for v in (vx[sel], vy[sel], vz[sel]):
+        mean = np.sum(w * v) / np.sum(w)
+        out.append(m * np.sum(w * (v - mean) ** 2) / np.sum(w))
+    return np.array(out)
