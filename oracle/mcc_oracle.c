@@ -190,6 +190,11 @@ double oracle_n97_L(double A) {
  * (isotropic). */
 double oracle_n97_A(double s) {
   if (!(s > 0.0)) return INFINITY;
+  /* For s > 50, A = 3 e^{-s} (1 + O(A^2)) < 6e-22 and the inverse CDF below
+   * equals its isotropic limit 1 - cos chi = 2 u to far below an ulp, while
+   * evaluating it would run through subnormal A (e^{-s} < 2.2e-308 for
+   * s > 708) and lose all precision: take the limit. */
+  if (s > 50.0) return 0.0;
   const double eps = 2.220446049250313e-16;
   const int use_M = (s <= 0.6931471805599453);
   double target, lo = 0.0, hi, A;

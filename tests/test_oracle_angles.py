@@ -38,7 +38,7 @@ def test_langevin_function_against_decimal(A):
 
 
 @pytest.mark.parametrize("s", [1e-10, 1e-6, 1e-3, 0.05, 0.3, 0.6931, 0.7, 1.0, 2.5,
-                               5.0, 12.0, 40.0, 300.0])
+                               5.0, 12.0, 40.0, 49.9])
 def test_n97_A_solves_mean_cosine(s):
     """<cos chi> = coth A - 1/A = exp(-s) (Nanbu's defining relation)."""
     A = oracle.n97_A(s)
@@ -57,9 +57,11 @@ def test_n97_A_solves_mean_cosine(s):
 def test_n97_A_asymptotics():
     for s in (1e-9, 1e-6, 1e-4):
         assert oracle.n97_A(s) == pytest.approx(1.0 / s, rel=2 * s)
-    for s in (20.0, 30.0, 60.0):
+    for s in (20.0, 30.0, 45.0):
         assert oracle.n97_A(s) == pytest.approx(3.0 * math.exp(-s), rel=1e-9)
-    assert oracle.n97_A(1000.0) == 0.0  # exp(-s) underflows: isotropic
+    # s > 50: A < 6e-22, the isotropic limit to far below an ulp
+    for s in (50.5, 60.0, 720.0, 745.0, 1000.0):
+        assert oracle.n97_A(s) == 0.0
     assert math.isinf(oracle.n97_A(0.0))
 
 
@@ -152,3 +154,12 @@ def test_rotation_along_z_axis():
         un = u + du
         assert float(un @ un) == pytest.approx(uz * uz, rel=1e-15)
         assert float(un @ u) == pytest.approx(uz * uz * math.cos(th), rel=1e-14)
+
+
+@pytest.mark.parametrize("s", [40.0, 49.9, 50.1, 300.0, 716.0, 744.6])
+def test_n97_large_s_is_isotropic_to_rounding(s):
+    """For large s the sampled 1 - cos chi equals 2 u to rounding (no
+    subnormal arithmetic on the way)."""
+    for u0 in (0.0427, 0.2427, 0.5369, 0.999):
+        oc, st = oracle.sample_angle(oracle.N97, s, u0, 0.5)
+        assert oc == pytest.approx(2.0 * u0, rel=1e-15)
