@@ -1,0 +1,233 @@
+/*
+ * mcc.h -- C ABI of libmcc_hip.so: the weighted, moment-preserving
+ * binary-pairing Monte-Carlo Coulomb collision step on MI355X (gfx950).
+ *
+ * Method: J. R. Angus, Y. Fu, V. Geyko, D. Grote, D. Larson,
+ * "Moment-preserving Monte-Carlo Coulomb collision method for particle codes"
+ * (arXiv 2407.19151).  One call applies one time step of the paper's
+ * Algorithm 1 to every cell: random binary pairing (Fig. 1, Sec. 3.2),
+ * weighted TA77/N97 scatter with w_min/w_max acceptance (Eq. (12),
+ * Secs. 3.1-3.2), momentum restore (Eq. (17)), energy-violation partition
+ * (Eqs. (18), (24)) and zero-angle inelastic pair energy correction
+ * (Eqs. (19)-(23)); relativistic variant of Appendix A; failure fallback of
+ * Sec. 6.2.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked "device" are HIP device (or managed) pointers; the
+ *    caller owns them; the library never frees or retains them past the call.
+ *  - Work is enqueued on the context's stream and the call returns without
+ *    waiting; outputs are valid after the stream is synchronized.
+ *  - Velocities are FP64 structure-of-arrays and are updated in place in all
+ *    precision modes.  In relativistic mode they hold the proper velocity
+ *    u = gamma v.
+ *  - Errors are returned as mcc_status; nothing is thrown across the ABI.
+ *    Host-checkable arguments are checked on every call.  Data-dependent
+ *    checks (offsets monotone, ids in range, cell sizes within the supported
+ *    maximum) run on the device; a violating cell is skipped, never read out
+ *    of bounds, and the first such code is latched in the context; read it
+ *    with mcc_device_error.  With the environment variable MCC_VALIDATE=1 the
+ *    collide calls synchronize and return that code themselves.
+ *  - An energy-correction failure is not an error: it is handled by
+ *    on_failure and counted in mcc_stats.failed.
+ *  - Random numbers are Philox4x32-10 keyed by seed, with counters built from
+ *    (index, cell, step, collision, purpose); results do not depend on how
+ *    cells are split across calls or GPUs.
+ */
+#ifndef MCC_H
+#define MCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MCC_OK = 0,
+  MCC_ERR_INVALID = -1,     /* bad argument (host check) */
+  MCC_ERR_OOM = -2,         /* device allocation failed */
+  MCC_ERR_DEVICE = -3,      /* HIP runtime error */
+  MCC_ERR_UNSUPPORTED = -4, /* valid but not supported combination */
+  MCC_ERR_DATA = -5         /* device-side data check failed (see mcc_device_error) */
+} mcc_status;
+
+typedef enum { MCC_TA77 = 0, MCC_N97 = 1 } mcc_method;
+typedef enum { MCC_FP64 = 0, MCC_FP32_KINEMATICS = 1 } mcc_precision;
+typedef enum { MCC_FAIL_RESET = 0, MCC_FAIL_KEEP = 1 } mcc_fail_policy;
+
+#define MCC_MAX_SPECIES 8
+#define MCC_MAX_COLLISIONS 32
+/* largest number of particles in one cell (all species) */
+#define MCC_MAX_CELL 32768
+
+/* Physical (unweighted) mass and charge of a species. */
+typedef struct {
+  double mass;
+  double charge;
+} mcc_species;
+
+/* One collision of the step: species a with species b (a == b: intra-species).
+ * Collisions are applied in list order; velocities carry over. */
+typedef struct {
+  int32_t a;
+  int32_t b;
+} mcc_collision;
+
+typedef struct {
+  int32_t method;            /* mcc_method: angle map from s (Sec. 3.2) */
+  int32_t precision;         /* mcc_precision: FP32 pair kinematics, FP64 state/sums/correction */
+  int32_t relativistic;      /* 1: arrays hold u = gamma v, Appendix A; needs c */
+  int32_t moment_correction; /* 1: Eqs. (17)-(24) after the scatter */
+  int32_t sort_by_weight;    /* 1: descending-weight order for the energy pairs (Alg. 1) */
+  int32_t max_passes;        /* passes of the energy-pair loop, >= 1 (default 1) */
+  int32_t on_failure;        /* mcc_fail_policy (Sec. 6.2) */
+  int32_t diagnostics;       /* 1: measure residual momentum/energy per collision into stats */
+  double f_E;                /* energy-correction factor, 0 < f_E < 1 (Eq. (23); default 0.05) */
+  double eps0;               /* vacuum permittivity in the caller's units (default 1) */
+  double c;                  /* speed of light (relativistic only) */
+} mcc_params;
+
+/* Step counters; lives in DEVICE memory, accumulated by the kernels.  The
+ * collide calls zero it first. */
+typedef struct {
+  unsigned long long pairs;      /* binary scatter pairs formed */
+  unsigned long long corr_pairs; /* energy-correction pairs with U != 0 */
+  unsigned long long failed;     /* (cell, collision) energy-correction failures */
+  unsigned long long collisions; /* (cell, collision) applications with pairs */
+  double max_rel_dP;             /* diagnostics: max residual |dP| / sum m w |v| */
+  double max_rel_dE;             /* diagnostics: max residual |dE| / KE */
+} mcc_stats;
+
+typedef struct mcc_ctx mcc_ctx;
+typedef struct mcc_plan mcc_plan;
+
+/* Defaults: N97, FP64, non-relativistic, correction on, sort on, one pass,
+ * reset on failure, no diagnostics, f_E = 0.05, eps0 = 1, c = 0. */
+void mcc_default_params(mcc_params *p);
+
+const char *mcc_status_string(mcc_status s);
+
+/* Create a context on `device` enqueuing on `hip_stream` (NULL: the default
+ * stream).  The context owns its workspace (cell work lists, error word,
+ * large-cell scratch), grown on demand. */
+mcc_status mcc_create(mcc_ctx **ctx, int device, void *hip_stream);
+mcc_status mcc_set_stream(mcc_ctx *ctx, void *hip_stream);
+void mcc_destroy(mcc_ctx *ctx);
+
+/* Synchronize the context's stream and return the first device-side data
+ * error code latched since the last call (0 if none), then clear it.
+ * Codes: 1 offsets not monotone or out of [0, n]; 2 cell larger than
+ * MCC_MAX_CELL; 3 cell or species id out of range (unsorted entry). */
+mcc_status mcc_device_error(mcc_ctx *ctx, int32_t *code);
+
+/*
+ * Kernel variant used for cells of size bucket `bucket` (0..6: cells with at
+ * most 128, 256, 512, 1024, 2048, 4096, MCC_MAX_CELL particles) by the
+ * non-plan entry points.  `variant` indexes the compiled (threads per cell,
+ * capacity) table: 0 (64,128), 1 (64,256), 2 (128,256), 3 (128,512),
+ * 4 (256,512), 5 (256,1024), 6 (512,1024), 7 (512,2048), 8 (1024,2048),
+ * 9 (1024,4096, global scratch), 10 (1024,32768, global scratch); -1 restores
+ * the default.  The variant's capacity must hold the bucket's largest cell,
+ * else MCC_ERR_INVALID.  Results agree between variants to rounding (the
+ * order of the per-cell sums depends on the threads per cell).
+ */
+mcc_status mcc_set_variant(mcc_ctx *ctx, int32_t bucket, int32_t variant);
+
+/*
+ * The device's polar-angle sampler alone (Sec. 3.2: the map from the
+ * normalized scattering length s to the centre-of-mass angle), for testing
+ * it against a reference: for i < n, with uniforms from the 32-bit words
+ * a0[i], a1[i] (the same conversion as the collision step), writes
+ * oc[i] = 1 - cos(theta) and st[i] = sin(theta), and for N97 A[i] (Nanbu's
+ * A(s); may be NULL).  All pointers are device memory; precision selects the
+ * FP64 or FP32 kinematics code.
+ */
+mcc_status mcc_sample_angles(mcc_ctx *ctx, int32_t method, int32_t precision, int64_t n,
+                             const double *s, const uint32_t *a0, const uint32_t *a1,
+                             double *oc, double *st, double *A);
+
+/*
+ * One step on particles grouped by (cell, species) -- Algorithm 1.
+ *  n            number of particles
+ *  n_cells, n_species (1..MCC_MAX_SPECIES)
+ *  offsets      device int64[n_cells*n_species + 1]; particles of cell c and
+ *               species s are [offsets[c*S+s], offsets[c*S+s+1])
+ *  weights      device double[n], w > 0 (Eq. (4): density w / dV)
+ *  vx, vy, vz   device double[n], in/out
+ *  cell_volume  device double[n_cells] or NULL to use cell_volume_scalar
+ *  species      host mcc_species[n_species]
+ *  coll         host mcc_collision[n_coll], n_coll <= MCC_MAX_COLLISIONS
+ *  dt, coulomb_log  time step and lnL of Eq. (12)
+ *  seed, step   Philox key and step counter
+ *  p            host parameters
+ *  stats        device mcc_stats* or NULL
+ *  cell_corr_pairs  device int32[n_cells] or NULL: energy-correction pairs
+ *               used per cell this step (the count of Sec. 5.1)
+ */
+mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells,
+                              int32_t n_species, const int64_t *offsets,
+                              const double *weights, double *vx, double *vy,
+                              double *vz, const double *cell_volume,
+                              double cell_volume_scalar,
+                              const mcc_species *species, int32_t n_coll,
+                              const mcc_collision *coll, double dt,
+                              double coulomb_log, uint64_t seed, uint64_t step,
+                              const mcc_params *p, mcc_stats *stats,
+                              int32_t *cell_corr_pairs);
+
+/*
+ * One step on particles in any order: cells, species_id are device
+ * int32[n].  Particles are grouped by (cell, species) keeping ascending
+ * index order inside each group, the sorted step is applied, and the
+ * velocities are written back in place.  Same other arguments.
+ */
+mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells,
+                       const int32_t *species_id, int32_t n_cells,
+                       int32_t n_species, const double *weights, double *vx,
+                       double *vy, double *vz, const double *cell_volume,
+                       double cell_volume_scalar, const mcc_species *species,
+                       int32_t n_coll, const mcc_collision *coll, double dt,
+                       double coulomb_log, uint64_t seed, uint64_t step,
+                       const mcc_params *p, mcc_stats *stats,
+                       int32_t *cell_corr_pairs);
+
+/*
+ * Cell binning alone (the grouping used by mcc_collide):
+ *  offsets_out  device int64[n_cells*n_species + 1]
+ *  perm_out     device int32[n]: perm_out[j] = original index of the j-th
+ *               particle in grouped order (ascending within each group)
+ */
+mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells,
+                   const int32_t *species_id, int32_t n_cells,
+                   int32_t n_species, int64_t *offsets_out, int32_t *perm_out);
+
+/*
+ * Batched form: a plan binds the sorted arrays of one particle population
+ * (same pointers every step), sorts its cells into size buckets on the
+ * device, picks threads-per-cell for each bucket (autotune = 1 times the
+ * candidates on this population; 0 uses the built-in table), and captures
+ * one step into a HIP graph.  mcc_plan_run replays it n_steps times with
+ * steps first_step, first_step+1, ...  The plan holds the offsets and the
+ * weights by pointer: if they change, destroy and re-create it.
+ */
+mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n,
+                           int32_t n_cells, int32_t n_species,
+                           const int64_t *offsets, const double *weights,
+                           double *vx, double *vy, double *vz,
+                           const double *cell_volume, double cell_volume_scalar,
+                           const mcc_species *species, int32_t n_coll,
+                           const mcc_collision *coll, double dt,
+                           double coulomb_log, uint64_t seed,
+                           const mcc_params *p, mcc_stats *stats,
+                           int32_t *cell_corr_pairs, int32_t autotune);
+mcc_status mcc_plan_run(mcc_plan *plan, uint64_t first_step, int32_t n_steps);
+/* Text description of the buckets and the chosen kernel variants. */
+mcc_status mcc_plan_describe(mcc_plan *plan, char *buf, size_t len);
+void mcc_plan_destroy(mcc_plan *plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCC_H */

@@ -1,0 +1,685 @@
+// mcc_api.hip -- host runtime behind include/mcc.h: context and workspace,
+// argument checks, per-collision constants, size-bucketed launches of the
+// collide kernel variants, the unsorted entry (binning + gather/scatter),
+// and the batched plan (device work lists, autotuned variants, HIP graph).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mcc.h"
+#include "mcc_kernel_args.hpp"
+#include "mcc_variants.hpp"
+
+const void *const *mcc_kernel_table_fp64();
+const void *const *mcc_kernel_table_fp32();
+const void *const *mcc_kernel_table_rel();
+
+namespace mcc {
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_zero_stats(mcc_stats *st, hipStream_t s);
+hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
+hipError_t launch_inc_u64(uint64_t *p, hipStream_t s);
+hipError_t launch_bucket_cells(const int64_t *offsets, int32_t n_cells, int32_t S, int64_t n,
+                               int32_t *lists, uint32_t *counts, int32_t *cell_corr, int32_t *err,
+                               hipStream_t s);
+int64_t scan_tiles_needed(int64_t m);
+uint64_t canon_scratch_words();
+hipError_t launch_bin(int64_t n, const int32_t *cells, const int32_t *species, int32_t n_cells,
+                      int32_t S, uint32_t *counts, int64_t *tiles, int64_t *offsets,
+                      unsigned long long *cursor, int32_t *perm, int32_t *big_list,
+                      uint32_t *big_count, uint32_t *canon_scr, int canon_big_grid, int32_t *err,
+                      hipStream_t s);
+hipError_t launch_sample_angles(int method, int precision, int64_t n, const double *s,
+                                const uint32_t *a0, const uint32_t *a1, double *oc, double *st,
+                                double *A, hipStream_t st_);
+hipError_t launch_gather(int64_t n, const int32_t *perm, const double *w, const double *vx,
+                         const double *vy, const double *vz, double *gw, double *gx, double *gy,
+                         double *gz, hipStream_t s);
+hipError_t launch_scatter_back(int64_t n, const int32_t *perm, const double *gx,
+                               const double *gy, const double *gz, double *vx, double *vy,
+                               double *vz, hipStream_t s);
+}  // namespace mcc
+
+using namespace mcc;
+
+namespace {
+
+constexpr int CANON_BIG_GRID = 16;
+constexpr int BIG32K_GRID = 32;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  bool ensure(size_t want) {
+    if (want <= bytes) return true;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (hipMalloc(&p, want) != hipSuccess) {
+      p = nullptr;
+      return false;
+    }
+    bytes = want;
+    return true;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T *as() const {
+    return reinterpret_cast<T *>(p);
+  }
+};
+
+const void *const *kernel_table(int mode) {
+  switch (mode) {
+    case MODE_FP64: return mcc_kernel_table_fp64();
+    case MODE_FP32: return mcc_kernel_table_fp32();
+    default: return mcc_kernel_table_rel();
+  }
+}
+
+}  // namespace
+
+struct mcc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  bool validate = false;
+  int32_t *err = nullptr;  // device error word
+  DevBuf lists, counts, big4k, big32k;
+  // unsorted entry
+  DevBuf ucnt, tiles, off, cursor, perm, biglist, bigcount, canon, gw, gx, gy, gz;
+  int grid[NMODE][NVARIANT] = {};
+  int variant[NBUCKET] = {};
+};
+
+struct mcc_plan {
+  mcc_ctx *ctx = nullptr;
+  CollideArgs args{};
+  int mode = 0;
+  int32_t n_cells = 0;
+  int variant[NBUCKET] = {};
+  DevBuf lists, counts, step;
+  mcc_stats *stats = nullptr;
+  int32_t *cell_corr = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double tuned_ms[NBUCKET][NVARIANT] = {};
+};
+
+namespace {
+
+mcc_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return MCC_OK;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return MCC_ERR_OOM;
+  return MCC_ERR_DEVICE;
+}
+
+#define HIP_TRY(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return from_hip(e_); \
+  } while (0)
+
+int mode_of(const mcc_params *p) {
+  if (p->relativistic) return MODE_REL;
+  return p->precision == MCC_FP32_KINEMATICS ? MODE_FP32 : MODE_FP64;
+}
+
+// host checks of the step arguments shared by every entry point
+mcc_status check_step(int64_t n, int32_t n_cells, int32_t n_species, const double *w,
+                      const double *vx, const double *vy, const double *vz,
+                      const double *cell_volume, double dVs, const mcc_species *sp,
+                      int32_t n_coll, const mcc_collision *coll, double dt, double lnL,
+                      const mcc_params *p) {
+  if (n < 0 || n_cells < 0 || n_species < 1 || n_species > MCC_MAX_SPECIES) return MCC_ERR_INVALID;
+  if (n_coll < 0 || n_coll > MCC_MAX_COLLISIONS) return MCC_ERR_INVALID;
+  if (n > 0 && (!w || !vx || !vy || !vz)) return MCC_ERR_INVALID;
+  if (n > (int64_t)INT32_MAX) return MCC_ERR_UNSUPPORTED;
+  if (!sp || (n_coll > 0 && !coll) || !p) return MCC_ERR_INVALID;
+  for (int s = 0; s < n_species; ++s)
+    if (!(sp[s].mass > 0.0) || !std::isfinite(sp[s].mass) || !std::isfinite(sp[s].charge))
+      return MCC_ERR_INVALID;
+  for (int k = 0; k < n_coll; ++k)
+    if (coll[k].a < 0 || coll[k].a >= n_species || coll[k].b < 0 || coll[k].b >= n_species)
+      return MCC_ERR_INVALID;
+  if (!std::isfinite(dt) || dt < 0.0 || !std::isfinite(lnL) || lnL < 0.0) return MCC_ERR_INVALID;
+  if (p->method != MCC_TA77 && p->method != MCC_N97) return MCC_ERR_INVALID;
+  if (p->precision != MCC_FP64 && p->precision != MCC_FP32_KINEMATICS) return MCC_ERR_INVALID;
+  if (p->on_failure != MCC_FAIL_RESET && p->on_failure != MCC_FAIL_KEEP) return MCC_ERR_INVALID;
+  if (p->max_passes < 1) return MCC_ERR_INVALID;
+  if (!(p->f_E > 0.0 && p->f_E < 1.0)) return MCC_ERR_INVALID;
+  if (!(p->eps0 > 0.0) || !std::isfinite(p->eps0)) return MCC_ERR_INVALID;
+  if (p->relativistic && !(p->c > 0.0 && std::isfinite(p->c))) return MCC_ERR_INVALID;
+  if (p->relativistic && p->precision != MCC_FP64) return MCC_ERR_UNSUPPORTED;
+  if (!cell_volume && !(dVs > 0.0 && std::isfinite(dVs))) return MCC_ERR_INVALID;
+  return MCC_OK;
+}
+
+void fill_args(CollideArgs &A, int64_t n, int32_t n_cells, int32_t S, const int64_t *offsets,
+               const double *w, double *vx, double *vy, double *vz, const double *cell_volume,
+               double dVs, const mcc_species *sp, int32_t n_coll, const mcc_collision *coll,
+               double dt, double lnL, uint64_t seed, uint64_t step, const mcc_params *p,
+               mcc_stats *stats, int32_t *cell_corr, int32_t *err) {
+  std::memset(&A, 0, sizeof(A));
+  A.offsets = offsets;
+  A.w = w;
+  A.vx = vx;
+  A.vy = vy;
+  A.vz = vz;
+  A.cell_volume = cell_volume;
+  A.dV = dVs;
+  A.n = n;
+  A.n_cells = n_cells;
+  A.S = S;
+  A.n_coll = n_coll;
+  A.method = p->method;
+  A.corr = p->moment_correction ? 1 : 0;
+  A.sortw = p->sort_by_weight ? 1 : 0;
+  A.max_passes = p->max_passes;
+  A.keep = p->on_failure == MCC_FAIL_KEEP ? 1 : 0;
+  A.diag = (p->diagnostics && stats) ? 1 : 0;
+  A.fE = p->f_E;
+  A.c = p->relativistic ? p->c : 1.0;
+  A.seed = seed;
+  A.step = step;
+  A.step_dev = nullptr;
+  for (int s = 0; s < S; ++s) A.mass[s] = sp[s].mass;
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < n_coll; ++k) {
+    const int a = coll[k].a, b = coll[k].b;
+    const double ma = sp[a].mass, mb = sp[b].mass, qa = sp[a].charge, qb = sp[b].charge;
+    const double mu = ma * mb / (ma + mb);
+    CollConst &C = A.coll[k];
+    C.a = a;
+    C.b = b;
+    // Eq. (12) without the per-pair factors f, w_max, N_min, dV and |u|^3
+    const double base = qa * qa * qb * qb * lnL * dt / (4.0 * pi * p->eps0 * p->eps0);
+    C.coef = p->relativistic ? base : base / (mu * mu);
+    C.fa = mb / (ma + mb);
+    C.fb = ma / (ma + mb);
+  }
+  A.stats = stats;
+  A.cell_corr = cell_corr;
+  A.err = err;
+}
+
+bool ensure_lists(mcc_ctx *ctx, DevBuf &lists, DevBuf &counts, int32_t n_cells) {
+  return lists.ensure(sizeof(int32_t) * (size_t)NBUCKET * (size_t)std::max(n_cells, 1)) &&
+         counts.ensure(sizeof(uint32_t) * 16);
+}
+
+// global-layout variants: persistent grid and per-workgroup scratch
+int grid_of(mcc_ctx *ctx, int mode, int v) {
+  const Variant V = variant_of(mode, v);
+  if (V.layout == 2) return V.cap > 4096 ? BIG32K_GRID : ctx->n_cu;
+  return ctx->grid[mode][v];
+}
+
+bool ensure_big(mcc_ctx *ctx, int mode, int v) {
+  const Variant V = variant_of(mode, v);
+  if (V.layout != 2) return true;
+  const uint64_t stride = big_stride_bytes(V.cap);
+  if (V.cap > 4096) return ctx->big32k.ensure(stride * BIG32K_GRID);
+  return ctx->big4k.ensure(stride * (uint64_t)ctx->n_cu);
+}
+
+void set_big_args(mcc_ctx *ctx, CollideArgs &A, int mode, int v) {
+  const Variant V = variant_of(mode, v);
+  if (V.layout != 2) return;
+  A.big_scratch = V.cap > 4096 ? ctx->big32k.as<char>() : ctx->big4k.as<char>();
+  A.big_stride = big_stride_bytes(V.cap);
+}
+
+// enqueue the collide kernels of all buckets, reading their device work lists
+mcc_status launch_buckets(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_t n_cells,
+                          const int32_t *lists, const uint32_t *counts, const int *variant,
+                          hipStream_t stream) {
+  const void *const *tab = kernel_table(mode);
+  for (int b = NBUCKET - 1; b >= 0; --b) {
+    const int v = variant[b];
+    if (!ensure_big(ctx, mode, v)) return MCC_ERR_OOM;
+    CollideArgs A = base;
+    A.cell_list = lists + (int64_t)b * std::max(n_cells, 1);
+    A.cell_count = counts + b;
+    set_big_args(ctx, A, mode, v);
+    void *kargs[] = {&A};
+    HIP_TRY(hipLaunchKernel(tab[v], dim3(grid_of(ctx, mode, v)),
+                            dim3(variant_of(mode, v).tpc), kargs, 0, stream));
+  }
+  return MCC_OK;
+}
+
+mcc_status finish(mcc_ctx *ctx) {
+  if (!ctx->validate) return MCC_OK;
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  int32_t code = 0;
+  HIP_TRY(hipMemcpy(&code, ctx->err, sizeof(code), hipMemcpyDeviceToHost));
+  return code ? MCC_ERR_DATA : MCC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mcc_default_params(mcc_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->method = MCC_N97;
+  p->precision = MCC_FP64;
+  p->relativistic = 0;
+  p->moment_correction = 1;
+  p->sort_by_weight = 1;
+  p->max_passes = 1;
+  p->on_failure = MCC_FAIL_RESET;
+  p->diagnostics = 0;
+  p->f_E = 0.05;
+  p->eps0 = 1.0;
+  p->c = 0.0;
+}
+
+const char *mcc_status_string(mcc_status s) {
+  switch (s) {
+    case MCC_OK: return "ok";
+    case MCC_ERR_INVALID: return "invalid argument";
+    case MCC_ERR_OOM: return "device out of memory";
+    case MCC_ERR_DEVICE: return "HIP runtime error";
+    case MCC_ERR_UNSUPPORTED: return "unsupported combination";
+    case MCC_ERR_DATA: return "device-side data check failed";
+  }
+  return "unknown status";
+}
+
+mcc_status mcc_create(mcc_ctx **out, int device, void *hip_stream) {
+  if (!out) return MCC_ERR_INVALID;
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return MCC_ERR_INVALID;
+  HIP_TRY(hipSetDevice(device));
+  mcc_ctx *ctx = new mcc_ctx();
+  ctx->device = device;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  hipDeviceProp_t prop;
+  hipError_t e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    delete ctx;
+    return from_hip(e);
+  }
+  ctx->n_cu = prop.multiProcessorCount;
+  for (int b = 0; b < NBUCKET; ++b) ctx->variant[b] = kDefaultVariant[b];
+  const char *val = std::getenv("MCC_VALIDATE");
+  ctx->validate = val && val[0] == '1';
+  e = hipMalloc(&ctx->err, sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemset(ctx->err, 0, sizeof(int32_t));
+  if (e != hipSuccess) {
+    delete ctx;
+    return from_hip(e);
+  }
+  for (int m = 0; m < NMODE; ++m) {
+    const void *const *tab = kernel_table(m);
+    for (int v = 0; v < NVARIANT; ++v) {
+      int nb = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, tab[v], variant_of(m, v).tpc, 0);
+      if (e != hipSuccess || nb < 1) nb = 1;
+      ctx->grid[m][v] = nb * ctx->n_cu;
+    }
+  }
+  *out = ctx;
+  return MCC_OK;
+}
+
+mcc_status mcc_set_stream(mcc_ctx *ctx, void *hip_stream) {
+  if (!ctx) return MCC_ERR_INVALID;
+  ctx->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return MCC_OK;
+}
+
+void mcc_destroy(mcc_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->big4k, &ctx->big32k, &ctx->ucnt, &ctx->tiles,
+                    &ctx->off, &ctx->cursor, &ctx->perm, &ctx->biglist, &ctx->bigcount,
+                    &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz})
+    b->release();
+  if (ctx->err) (void)hipFree(ctx->err);
+  delete ctx;
+}
+
+mcc_status mcc_set_variant(mcc_ctx *ctx, int32_t bucket, int32_t variant) {
+  if (!ctx || bucket < 0 || bucket >= NBUCKET || variant < -1 || variant >= NVARIANT)
+    return MCC_ERR_INVALID;
+  if (variant == -1) {
+    ctx->variant[bucket] = kDefaultVariant[bucket];
+    return MCC_OK;
+  }
+  if (kVariants[variant].cap < kBucketCap[bucket]) return MCC_ERR_INVALID;
+  ctx->variant[bucket] = variant;
+  return MCC_OK;
+}
+
+mcc_status mcc_sample_angles(mcc_ctx *ctx, int32_t method, int32_t precision, int64_t n,
+                             const double *s, const uint32_t *a0, const uint32_t *a1, double *oc,
+                             double *st, double *A) {
+  if (!ctx || n < 0 || (method != MCC_TA77 && method != MCC_N97) ||
+      (precision != MCC_FP64 && precision != MCC_FP32_KINEMATICS))
+    return MCC_ERR_INVALID;
+  if (n > 0 && (!s || !a0 || !a1 || !oc || !st)) return MCC_ERR_INVALID;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(launch_sample_angles(method, precision, n, s, a0, a1, oc, st, A, ctx->stream));
+  return finish(ctx);
+}
+
+mcc_status mcc_device_error(mcc_ctx *ctx, int32_t *code) {
+  if (!ctx || !code) return MCC_ERR_INVALID;
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipMemcpy(code, ctx->err, sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemset(ctx->err, 0, sizeof(int32_t)));
+  return MCC_OK;
+}
+
+mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                              const int64_t *offsets, const double *weights, double *vx,
+                              double *vy, double *vz, const double *cell_volume,
+                              double cell_volume_scalar, const mcc_species *species,
+                              int32_t n_coll, const mcc_collision *coll, double dt,
+                              double coulomb_log, uint64_t seed, uint64_t step,
+                              const mcc_params *p, mcc_stats *stats, int32_t *cell_corr_pairs) {
+  if (!ctx || !offsets) return MCC_ERR_INVALID;
+  mcc_status st = check_step(n, n_cells, n_species, weights, vx, vy, vz, cell_volume,
+                             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, p);
+  if (st != MCC_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (!ensure_lists(ctx, ctx->lists, ctx->counts, n_cells)) return MCC_ERR_OOM;
+  CollideArgs A;
+  fill_args(A, n, n_cells, n_species, offsets, weights, vx, vy, vz, cell_volume,
+            cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, seed, step, p, stats,
+            cell_corr_pairs, ctx->err);
+  hipStream_t s = ctx->stream;
+  HIP_TRY(launch_fill_u32(ctx->counts.as<uint32_t>(), 0u, NBUCKET, s));
+  if (stats) HIP_TRY(launch_zero_stats(stats, s));
+  if (n_cells == 0) return finish(ctx);
+  HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, ctx->lists.as<int32_t>(),
+                              ctx->counts.as<uint32_t>(), cell_corr_pairs, ctx->err, s));
+  st = launch_buckets(ctx, A, mode_of(p), n_cells, ctx->lists.as<int32_t>(),
+                      ctx->counts.as<uint32_t>(), ctx->variant, s);
+  if (st != MCC_OK) return st;
+  return finish(ctx);
+}
+
+static mcc_status bin_into(mcc_ctx *ctx, int64_t n, const int32_t *cells,
+                           const int32_t *species_id, int32_t n_cells, int32_t n_species,
+                           int64_t *offsets, int32_t *perm) {
+  const int64_t m = (int64_t)n_cells * n_species;
+  if (!ctx->ucnt.ensure(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1)) ||
+      !ctx->tiles.ensure(sizeof(int64_t) * (size_t)scan_tiles_needed(m)) ||
+      !ctx->cursor.ensure(sizeof(unsigned long long) * (size_t)std::max<int64_t>(m, 1)) ||
+      !ctx->biglist.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1)) ||
+      !ctx->bigcount.ensure(sizeof(uint32_t) * 4) ||
+      !ctx->canon.ensure(sizeof(uint32_t) * canon_scratch_words() * CANON_BIG_GRID))
+    return MCC_ERR_OOM;
+  return from_hip(launch_bin(n, cells, species_id, n_cells, n_species, ctx->ucnt.as<uint32_t>(),
+                             ctx->tiles.as<int64_t>(), offsets,
+                             ctx->cursor.as<unsigned long long>(), perm,
+                             ctx->biglist.as<int32_t>(), ctx->bigcount.as<uint32_t>(),
+                             ctx->canon.as<uint32_t>(), CANON_BIG_GRID, ctx->err, ctx->stream));
+}
+
+mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int32_t *species_id,
+                   int32_t n_cells, int32_t n_species, int64_t *offsets_out, int32_t *perm_out) {
+  if (!ctx || n < 0 || n_cells < 0 || n_species < 1 || n_species > MCC_MAX_SPECIES ||
+      !offsets_out || (n > 0 && (!cells || !species_id || !perm_out)))
+    return MCC_ERR_INVALID;
+  if (n > (int64_t)INT32_MAX) return MCC_ERR_UNSUPPORTED;
+  HIP_TRY(hipSetDevice(ctx->device));
+  mcc_status st = bin_into(ctx, n, cells, species_id, n_cells, n_species, offsets_out, perm_out);
+  if (st != MCC_OK) return st;
+  return finish(ctx);
+}
+
+mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int32_t *species_id,
+                       int32_t n_cells, int32_t n_species, const double *weights, double *vx,
+                       double *vy, double *vz, const double *cell_volume,
+                       double cell_volume_scalar, const mcc_species *species, int32_t n_coll,
+                       const mcc_collision *coll, double dt, double coulomb_log, uint64_t seed,
+                       uint64_t step, const mcc_params *p, mcc_stats *stats,
+                       int32_t *cell_corr_pairs) {
+  if (!ctx || (n > 0 && (!cells || !species_id))) return MCC_ERR_INVALID;
+  mcc_status st = check_step(n, n_cells, n_species, weights, vx, vy, vz, cell_volume,
+                             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, p);
+  if (st != MCC_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int64_t m = (int64_t)n_cells * n_species;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  if (!ctx->off.ensure(sizeof(int64_t) * (size_t)(m + 1)) ||
+      !ctx->perm.ensure(sizeof(int32_t) * nn) || !ctx->gw.ensure(sizeof(double) * nn) ||
+      !ctx->gx.ensure(sizeof(double) * nn) || !ctx->gy.ensure(sizeof(double) * nn) ||
+      !ctx->gz.ensure(sizeof(double) * nn))
+    return MCC_ERR_OOM;
+  st = bin_into(ctx, n, cells, species_id, n_cells, n_species, ctx->off.as<int64_t>(),
+                ctx->perm.as<int32_t>());
+  if (st != MCC_OK) return st;
+  HIP_TRY(launch_gather(n, ctx->perm.as<int32_t>(), weights, vx, vy, vz, ctx->gw.as<double>(),
+                        ctx->gx.as<double>(), ctx->gy.as<double>(), ctx->gz.as<double>(),
+                        ctx->stream));
+  const bool v = ctx->validate;
+  ctx->validate = false;
+  st = mcc_collide_sorted(ctx, n, n_cells, n_species, ctx->off.as<int64_t>(),
+                          ctx->gw.as<double>(), ctx->gx.as<double>(), ctx->gy.as<double>(),
+                          ctx->gz.as<double>(), cell_volume, cell_volume_scalar, species, n_coll,
+                          coll, dt, coulomb_log, seed, step, p, stats, cell_corr_pairs);
+  ctx->validate = v;
+  if (st != MCC_OK) return st;
+  HIP_TRY(launch_scatter_back(n, ctx->perm.as<int32_t>(), ctx->gx.as<double>(),
+                              ctx->gy.as<double>(), ctx->gz.as<double>(), vx, vy, vz,
+                              ctx->stream));
+  return finish(ctx);
+}
+
+// ---------------------------------------------------------------------------
+// Batched plan
+// ---------------------------------------------------------------------------
+static mcc_status plan_enqueue_step(mcc_plan *pl, hipStream_t s) {
+  // counters are reset by kernels (no memset nodes in the graph)
+  if (pl->stats) HIP_TRY(launch_zero_stats(pl->stats, s));
+  mcc_status st = launch_buckets(pl->ctx, pl->args, pl->mode, pl->n_cells,
+                                 pl->lists.as<int32_t>(), pl->counts.as<uint32_t>(), pl->variant,
+                                 s);
+  if (st != MCC_OK) return st;
+  HIP_TRY(launch_inc_u64(pl->step.as<uint64_t>(), s));
+  return MCC_OK;
+}
+
+mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_cells,
+                           int32_t n_species, const int64_t *offsets, const double *weights,
+                           double *vx, double *vy, double *vz, const double *cell_volume,
+                           double cell_volume_scalar, const mcc_species *species, int32_t n_coll,
+                           const mcc_collision *coll, double dt, double coulomb_log, uint64_t seed,
+                           const mcc_params *p, mcc_stats *stats, int32_t *cell_corr_pairs,
+                           int32_t autotune) {
+  if (!ctx || !plan || !offsets) return MCC_ERR_INVALID;
+  *plan = nullptr;
+  mcc_status st = check_step(n, n_cells, n_species, weights, vx, vy, vz, cell_volume,
+                             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, p);
+  if (st != MCC_OK) return st;
+  HIP_TRY(hipSetDevice(ctx->device));
+  mcc_plan *pl = new mcc_plan();
+  pl->ctx = ctx;
+  pl->mode = mode_of(p);
+  pl->n_cells = n_cells;
+  pl->stats = stats;
+  pl->cell_corr = cell_corr_pairs;
+  for (int b = 0; b < NBUCKET; ++b) pl->variant[b] = kDefaultVariant[b];
+  if (!ensure_lists(ctx, pl->lists, pl->counts, n_cells) || !pl->step.ensure(64)) {
+    mcc_plan_destroy(pl);
+    return MCC_ERR_OOM;
+  }
+  fill_args(pl->args, n, n_cells, n_species, offsets, weights, vx, vy, vz, cell_volume,
+            cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, seed, 0, p, stats,
+            cell_corr_pairs, ctx->err);
+  pl->args.step_dev = pl->step.as<uint64_t>();
+  hipStream_t s = ctx->stream;
+  // device work lists, built once (offsets are fixed for the plan)
+  hipError_t e = launch_fill_u32(pl->counts.as<uint32_t>(), 0u, NBUCKET, s);
+  if (e == hipSuccess && n_cells > 0)
+    e = launch_bucket_cells(offsets, n_cells, n_species, n, pl->lists.as<int32_t>(),
+                            pl->counts.as<uint32_t>(), cell_corr_pairs, ctx->err, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    mcc_plan_destroy(pl);
+    return from_hip(e);
+  }
+  if (autotune && n_cells > 0) {
+    // time every candidate variant of every non-empty bucket on this
+    // population; the trial steps use a scratch copy of the velocities so the
+    // caller's state is untouched
+    uint32_t hcounts[NBUCKET];
+    e = hipMemcpy(hcounts, pl->counts.p, sizeof(hcounts), hipMemcpyDeviceToHost);
+    DevBuf tv;
+    const size_t nb = sizeof(double) * (size_t)std::max<int64_t>(n, 1);
+    if (e != hipSuccess || !tv.ensure(3 * nb)) {
+      mcc_plan_destroy(pl);
+      return e != hipSuccess ? from_hip(e) : MCC_ERR_OOM;
+    }
+    CollideArgs T = pl->args;
+    T.vx = tv.as<double>();
+    T.vy = T.vx + std::max<int64_t>(n, 1);
+    T.vz = T.vy + std::max<int64_t>(n, 1);
+    T.stats = nullptr;
+    T.cell_corr = nullptr;
+    T.step_dev = nullptr;
+    T.step = 0x7FFFFFFFull;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const void *const *tab = kernel_table(pl->mode);
+    for (int b = 0; b < NBUCKET && e == hipSuccess; ++b) {
+      if (hcounts[b] == 0) continue;
+      double best = 1e300;
+      for (int ci = 0; ci < 5 && kCandidates[b][ci] >= 0; ++ci) {
+        const int v = kCandidates[b][ci];
+        if (!ensure_big(ctx, pl->mode, v)) continue;
+        CollideArgs A = T;
+        A.cell_list = pl->lists.as<int32_t>() + (int64_t)b * std::max(n_cells, 1);
+        A.cell_count = pl->counts.as<uint32_t>() + b;
+        set_big_args(ctx, A, pl->mode, v);
+        void *kargs[] = {&A};
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+          e = hipMemcpyAsync(T.vx, vx, nb, hipMemcpyDeviceToDevice, s);
+          if (e == hipSuccess) e = hipMemcpyAsync(T.vy, vy, nb, hipMemcpyDeviceToDevice, s);
+          if (e == hipSuccess) e = hipMemcpyAsync(T.vz, vz, nb, hipMemcpyDeviceToDevice, s);
+          if (e == hipSuccess) e = hipEventRecord(e0, s);
+          if (e == hipSuccess)
+            e = hipLaunchKernel(tab[v], dim3(grid_of(ctx, pl->mode, v)),
+                                dim3(variant_of(pl->mode, v).tpc), kargs, 0, s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) ms_best = std::min(ms_best, ms);  // first run warms up
+        }
+        pl->tuned_ms[b][v] = ms_best;
+        if (ms_best < best) {
+          best = ms_best;
+          pl->variant[b] = v;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    tv.release();
+    if (e != hipSuccess) {
+      mcc_plan_destroy(pl);
+      return from_hip(e);
+    }
+  }
+  // workspace of every chosen variant exists before capture (no allocation
+  // while capturing)
+  for (int b = 0; b < NBUCKET; ++b)
+    if (!ensure_big(ctx, pl->mode, pl->variant[b])) {
+      mcc_plan_destroy(pl);
+      return MCC_ERR_OOM;
+    }
+  // capture one step into a graph: stats reset, bucket kernels, step += 1
+  hipStream_t cs;
+  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    st = plan_enqueue_step(pl, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &pl->graph);
+    if (st == MCC_OK && e2 != hipSuccess) st = from_hip(e2);
+    if (st == MCC_OK) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+  }
+  (void)hipStreamDestroy(cs);
+  if (e != hipSuccess || st != MCC_OK) {
+    mcc_plan_destroy(pl);
+    return st != MCC_OK ? st : from_hip(e);
+  }
+  *plan = pl;
+  return MCC_OK;
+}
+
+mcc_status mcc_plan_run(mcc_plan *pl, uint64_t first_step, int32_t n_steps) {
+  if (!pl || n_steps < 0) return MCC_ERR_INVALID;
+  HIP_TRY(hipSetDevice(pl->ctx->device));
+  hipStream_t s = pl->ctx->stream;
+  HIP_TRY(launch_set_u64(pl->step.as<uint64_t>(), first_step, s));
+  for (int i = 0; i < n_steps; ++i) HIP_TRY(hipGraphLaunch(pl->exec, s));
+  return finish(pl->ctx);
+}
+
+mcc_status mcc_plan_describe(mcc_plan *pl, char *buf, size_t len) {
+  if (!pl || !buf || len == 0) return MCC_ERR_INVALID;
+  uint32_t hc[NBUCKET] = {};
+  HIP_TRY(hipStreamSynchronize(pl->ctx->stream));
+  HIP_TRY(hipMemcpy(hc, pl->counts.p, sizeof(hc), hipMemcpyDeviceToHost));
+  std::string out = "{\"buckets\": [";
+  for (int b = 0; b < NBUCKET; ++b) {
+    const Variant V = variant_of(pl->mode, pl->variant[b]);
+    char tmp[512];
+    std::snprintf(tmp, sizeof(tmp),
+                  "%s{\"max_cell\": %d, \"cells\": %u, \"tpc\": %d, \"cap\": %d, \"layout\": %d, "
+                  "\"timed_ms\": {",
+                  b ? ", " : "", kBucketCap[b], hc[b], V.tpc, V.cap, V.layout);
+    out += tmp;
+    bool first = true;
+    for (int u = 0; u < NVARIANT; ++u) {
+      if (pl->tuned_ms[b][u] <= 0.0) continue;
+      const Variant U = variant_of(pl->mode, u);
+      std::snprintf(tmp, sizeof(tmp), "%s\"%dx%d\": %.4f", first ? "" : ", ", U.tpc, U.cap,
+                    pl->tuned_ms[b][u]);
+      out += tmp;
+      first = false;
+    }
+    out += "}}";
+  }
+  out += "]}";
+  std::snprintf(buf, len, "%s", out.c_str());
+  return MCC_OK;
+}
+
+void mcc_plan_destroy(mcc_plan *pl) {
+  if (!pl) return;
+  (void)hipSetDevice(pl->ctx->device);
+  (void)hipStreamSynchronize(pl->ctx->stream);
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  pl->lists.release();
+  pl->counts.release();
+  pl->step.release();
+  delete pl;
+}
+
+}  // extern "C"

@@ -1,0 +1,874 @@
+// mcc_collide.hpp -- the per-cell collision kernel (Algorithm 1 of the paper),
+// one workgroup per cell, cells taken from a size-bucketed work list.
+//
+// Template parameters:
+//   TPC  threads per cell (workgroup size, multiple of 64)
+//   CAP  largest cell (all species) this variant holds
+//   KR   type of the pair kinematics (double, or float for the FP32 form)
+//   REL  relativistic (Appendix A; FP64 only)
+//   LAY  where the cell lives: LAYOUT_LDS (everything in LDS), LAYOUT_COMPACT
+//        (LDS with aliased scratch and the weights read from the input, for
+//        cells up to 4096), LAYOUT_GLOBAL (per-workgroup global scratch; the
+//        workgroup is one wave so every exchange stays in program order)
+//
+// Data flow per cell: the cell's velocities and weights are staged in LDS
+// (coalesced loads), every collision of the list is applied in order, and
+// the velocities are written back once.  Pre-scatter velocities are kept in
+// the owner thread's registers (particle e is owned by thread e % TPC).
+#pragma once
+
+#include "mcc_device.hpp"
+#include "mcc_kernel_args.hpp"
+
+namespace mcc {
+
+// Where the arrays of a cell live (all cross-thread data is in LDS unless the
+// layout is GLOBAL, whose workgroup is a single wave).
+enum Layout : int { LAYOUT_LDS = 0, LAYOUT_COMPACT = 1, LAYOUT_GLOBAL = 2 };
+
+struct CellMem {
+  double *vx, *vy, *vz;
+  const double *w;        // LDS copy, or the read-only input (COMPACT)
+  uint16_t *list0, *list1, *ord0, *ord1, *mem;
+  uint32_t *key;          // shuffle keys (CAP)
+  uint32_t *cnt;          // CAP+1 bucket counters, always LDS (atomics)
+  double *kbuf;           // per-pair K / U of the energy loop (+ h(-mu) for REL)
+  uint32_t *slotbuf;      // GLOBAL: per-item bucket slots
+  double *bx, *by, *bz;   // GLOBAL: pre-scatter snapshot
+};
+
+// ---------------------------------------------------------------------------
+// Pair scatter (Sec. 3.1-3.2, Eq. (12)); non-relativistic
+// ---------------------------------------------------------------------------
+template <typename KR>
+__device__ __forceinline__ void scatter_pair_nr(const CellMem &M, int I, int J, uint32_t kp,
+                                                double coef_f_nmin_dV, const CollConst &C,
+                                                int method, uint32_t cell, uint32_t step_lo,
+                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+  using K = KMath<KR>;
+  const double vix = M.vx[I], viy = M.vy[I], viz = M.vz[I];
+  const double vjx = M.vx[J], vjy = M.vy[J], vjz = M.vz[J];
+  const double wi = M.w[I], wj = M.w[J];
+  const KR ux = (KR)(vix - vjx), uy = (KR)(viy - vjy), uz = (KR)(viz - vjz);
+  const KR um2 = ux * ux + uy * uy + uz * uz;
+  if (um2 == KR(0)) return;
+  const KR um = K::sqrt_(um2);
+  const double wmax = wi > wj ? wi : wj;
+  const KR s = (KR)(coef_f_nmin_dV * wmax) / (um2 * um);
+  if (!(s > KR(0))) return;
+  const U4 r = philox(kp, cell, step_lo, c3, k0, k1);
+  KR oc, st;
+  sample_angle<KR>(method, s, r.x, r.y, oc, st);
+  KR sp, cp;
+  K::sincos2pi(K::u(r.z), sp, cp);
+  KR dx, dy, dz;
+  rotate_delta<KR>(ux, uy, uz, st, oc, sp, cp, dx, dy, dz);
+  // acceptance of the heavier particle, decided in FP64 in every mode
+  const double u3 = unif64(r.w);
+  bool ai = true, aj = true;
+  if (wi < wj)
+    aj = u3 <= wi / wj;
+  else if (wj < wi)
+    ai = u3 <= wj / wi;
+  if (ai) {
+    M.vx[I] = vix + C.fa * (double)dx;
+    M.vy[I] = viy + C.fa * (double)dy;
+    M.vz[I] = viz + C.fa * (double)dz;
+  }
+  if (aj) {
+    M.vx[J] = vjx - C.fb * (double)dx;
+    M.vy[J] = vjy - C.fb * (double)dy;
+    M.vz[J] = vjz - C.fb * (double)dz;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Relativistic pair scatter (the paper gives none; see the design notes):
+// rotation of the pair's centre-of-momentum momentum p* by the sampled angle,
+// boosted back; s from the invariant rate with the CM deflection.
+// Species (unweighted) masses ma, mb; u = gamma v.  All FP64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void scatter_pair_rel(const CellMem &M, int I, int J, uint32_t kp,
+                                                 double coef_f_nmin_dV, double ma, double mb,
+                                                 double c, int method, uint32_t cell,
+                                                 uint32_t step_lo, uint32_t c3, uint32_t k0,
+                                                 uint32_t k1) {
+  const double c2 = c * c;
+  const double uix = M.vx[I], uiy = M.vy[I], uiz = M.vz[I];
+  const double ujx = M.vx[J], ujy = M.vy[J], ujz = M.vz[J];
+  const double wi = M.w[I], wj = M.w[J];
+  const double dx = uix - ujx, dy = uiy - ujy, dz = uiz - ujz;
+  const double du2 = dx * dx + dy * dy + dz * dz;
+  if (du2 == 0.0) return;
+  const double gi = sqrt(1.0 + (uix * uix + uiy * uiy + uiz * uiz) / c2);
+  const double gj = sqrt(1.0 + (ujx * ujx + ujy * ujy + ujz * ujz) / c2);
+  const double dus = dx * (uix + ujx) + dy * (uiy + ujy) + dz * (uiz + ujz);
+  const double dg = dus / (c2 * (gi + gj));  // gamma_i - gamma_j
+  const double gr1 = 0.5 * (du2 / c2 - dg * dg);  // gamma_rel - 1
+  if (!(gr1 > 0.0)) return;
+  const double sq = sqrt(gr1 * (gr1 + 2.0));
+  const double Mt = ma + mb;
+  const double ecm = sqrt(Mt * Mt + 2.0 * ma * mb * gr1);  // E_cm / c^2
+  const double etot = ma * gi + mb * gj;                   // E_tot / c^2
+  const double pstar = ma * mb * c * sq / ecm;
+  const double vM = c * sq / (gi * gj);
+  const double vrel = c * sq / (1.0 + gr1);
+  const double wmax = wi > wj ? wi : wj;
+  const double s = coef_f_nmin_dV * wmax * vM / (pstar * pstar * vrel * vrel);
+  if (!(s > 0.0)) return;
+  // p_i* = (E_j p_i - E_i p_j)/E_cm + p_tot x (p_j x p_i) / (c^2 E_cm (E_tot + E_cm))
+  const double mm = ma * mb;
+  const double Qx = mm * (gj * dx - dg * ujx), Qy = mm * (gj * dy - dg * ujy),
+               Qz = mm * (gj * dz - dg * ujz);
+  const double ptx = ma * uix + mb * ujx, pty = ma * uiy + mb * ujy, ptz = ma * uiz + mb * ujz;
+  const double jx = mm * (ujy * dz - ujz * dy), jy = mm * (ujz * dx - ujx * dz),
+               jz = mm * (ujx * dy - ujy * dx);  // p_j x p_i
+  const double crx = pty * jz - ptz * jy, cry = ptz * jx - ptx * jz, crz = ptx * jy - pty * jx;
+  const double kb = 1.0 / (c2 * ecm * (etot + ecm));
+  const double psx = Qx / ecm + crx * kb, psy = Qy / ecm + cry * kb, psz = Qz / ecm + crz * kb;
+  const U4 r = philox(kp, cell, step_lo, c3, k0, k1);
+  double oc, st;
+  sample_angle<double>(method, s, r.x, r.y, oc, st);
+  double sp, cp;
+  KMath<double>::sincos2pi(unif64(r.z), sp, cp);
+  double Dx, Dy, Dz;
+  rotate_delta<double>(psx, psy, psz, st, oc, sp, cp, Dx, Dy, Dz);
+  const double Dp = (Dx * ptx + Dy * pty + Dz * ptz) * kb;
+  const double px = Dx + Dp * ptx, py = Dy + Dp * pty, pz = Dz + Dp * ptz;
+  const double u3 = unif64(r.w);
+  bool ai = true, aj = true;
+  if (wi < wj)
+    aj = u3 <= wi / wj;
+  else if (wj < wi)
+    ai = u3 <= wj / wi;
+  if (ai) {
+    M.vx[I] = uix + px / ma;
+    M.vy[I] = uiy + py / ma;
+    M.vz[I] = uiz + pz / ma;
+  }
+  if (aj) {
+    M.vx[J] = ujx - px / mb;
+    M.vy[J] = ujy - py / mb;
+    M.vz[J] = ujz - pz / mb;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pair energy correction helpers (Eqs. (19)-(23); Appendix A)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double pair_K_nr(double m1, double m2, double ax, double ay, double az,
+                                            double bx, double by, double bz) {
+  const double mu = m1 * m2 / (m1 + m2);
+  const double rx = ax - bx, ry = ay - by, rz = az - bz;
+  return 0.5 * mu * (rx * rx + ry * ry + rz * rz);
+}
+
+// relativistic CM kinetic energy of the weighted pair
+__device__ __forceinline__ double pair_K_rel(double m1, double m2, double ax, double ay, double az,
+                                             double bx, double by, double bz, double c) {
+  const double c2 = c * c;
+  const double dx = ax - bx, dy = ay - by, dz = az - bz;
+  const double du2 = dx * dx + dy * dy + dz * dz;
+  const double g1 = sqrt(1.0 + (ax * ax + ay * ay + az * az) / c2);
+  const double g2 = sqrt(1.0 + (bx * bx + by * by + bz * bz) / c2);
+  const double dus = dx * (ax + bx) + dy * (ay + by) + dz * (az + bz);
+  const double dg = dus / (c2 * (g1 + g2));
+  double gr1 = 0.5 * (du2 / c2 - dg * dg);
+  if (gr1 < 0.0) gr1 = 0.0;
+  const double Mt = m1 + m2;
+  const double ecm = sqrt(Mt * Mt + 2.0 * m1 * m2 * gr1);
+  return 2.0 * m1 * m2 * c2 * gr1 / (ecm + Mt);
+}
+
+struct RelPair {
+  double p1x, p1y, p1z, p2x, p2y, p2z, dx, dy, dz, E1, E2, m1, m2, c2;
+  __device__ __forceinline__ void init(double m1_, double m2_, double ax, double ay, double az,
+                                       double bx, double by, double bz, double c) {
+    m1 = m1_;
+    m2 = m2_;
+    c2 = c * c;
+    dx = ax - bx;
+    dy = ay - by;
+    dz = az - bz;
+    p1x = m1 * ax;
+    p1y = m1 * ay;
+    p1z = m1 * az;
+    p2x = m2 * bx;
+    p2y = m2 * by;
+    p2z = m2 * bz;
+    E1 = m1 * c2 * sqrt(1.0 + (ax * ax + ay * ay + az * az) / c2);
+    E2 = m2 * c2 * sqrt(1.0 + (bx * bx + by * by + bz * bz) / c2);
+  }
+  // E1(alpha) + E2(alpha) - E1 - E2 (without U) and its derivative
+  __device__ __forceinline__ double h0(double al, double &dh) const {
+    const double a1x = p1x + al * dx, a1y = p1y + al * dy, a1z = p1z + al * dz;
+    const double a2x = p2x - al * dx, a2y = p2y - al * dy, a2z = p2z - al * dz;
+    const double E1n = sqrt(m1 * m1 * c2 * c2 + c2 * (a1x * a1x + a1y * a1y + a1z * a1z));
+    const double E2n = sqrt(m2 * m2 * c2 * c2 + c2 * (a2x * a2x + a2y * a2y + a2z * a2z));
+    const double p1d = p1x * dx + p1y * dy + p1z * dz;
+    const double p2d = p2x * dx + p2y * dy + p2z * dz;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    dh = c2 * ((a1x * dx + a1y * dy + a1z * dz) / E1n - (a2x * dx + a2y * dy + a2z * dz) / E2n);
+    return c2 * ((2.0 * al * p1d + al * al * d2) / (E1n + E1) +
+                 (-2.0 * al * p2d + al * al * d2) / (E2n + E2));
+  }
+  __device__ __forceinline__ double mu() const { return m1 * m2 / (m1 + m2); }
+};
+
+// alpha with E1' + E2' = E_tot - U on the branch alpha > -mu_R (Eq. (A.5));
+// the caller has checked that a root exists (h(-mu_R) <= 0 when U > 0).
+__device__ double rel_alpha(const RelPair &R, double U) {
+  const double muR = R.mu();
+  double dh, lo, hi;
+  if (U > 0.0) {
+    lo = -muR;
+    hi = 0.0;
+  } else {
+    lo = 0.0;
+    hi = muR;
+    for (int it = 0; it < 200 && R.h0(hi, dh) + U < 0.0; ++it) hi *= 2.0;
+  }
+  const double d2 = R.dx * R.dx + R.dy * R.dy + R.dz * R.dz;
+  const double x = U / (0.5 * muR * d2);
+  double a = (x < 1.0) ? muR * (-x / (1.0 + sqrt(1.0 - x))) : 0.5 * (lo + hi);
+  if (!(a > lo && a < hi)) a = 0.5 * (lo + hi);
+  const double eps = 2.220446049250313e-16;
+  for (int it = 0; it < 200; ++it) {
+    const double h = R.h0(a, dh) + U;
+    if (h == 0.0) break;
+    if (h > 0.0)
+      hi = a;
+    else
+      lo = a;
+    if (hi - lo <= 4.0 * eps * fabs(a)) break;
+    double an = a - h / dh;
+    if (!(an > lo && an < hi)) an = 0.5 * (lo + hi);
+    if (fabs(an - a) <= 0.5 * eps * fabs(a)) {
+      a = an;
+      break;
+    }
+    a = an;
+  }
+  return a;
+}
+
+// ---------------------------------------------------------------------------
+// Random permutation of one species list: ordered by (Philox word, index).
+// out[q] = cell-local particle index (off + item).
+// ---------------------------------------------------------------------------
+template <int TPC, int PPT, bool G>
+__device__ __forceinline__ void shuffle_species(const CellMem &M, int ns, int off, uint32_t cell,
+                                                uint32_t step_lo, uint32_t c3, uint32_t k0,
+                                                uint32_t k1, uint16_t *out, uint32_t *wsum,
+                                                uint32_t *maxocc) {
+  uint32_t *key = M.key;
+  uint32_t *cnt = M.cnt;
+  const int t = threadIdx.x;
+  for (int q = t; 4 * q < ns; q += TPC) {
+    const U4 r = philox((uint32_t)q, cell, step_lo, c3, k0, k1);
+    const int i = 4 * q;
+    key[i] = r.x;
+    if (i + 1 < ns) key[i + 1] = r.y;
+    if (i + 2 < ns) key[i + 2] = r.z;
+    if (i + 3 < ns) key[i + 3] = r.w;
+  }
+  __syncthreads();
+  const uint64_t nsu = (uint64_t)ns;
+  bucket_rank_sort<TPC, PPT, G>(
+      ns, cnt, M.mem, out, wsum, maxocc,
+      [&](int i) -> uint32_t { return (uint32_t)(((uint64_t)key[i] * nsu) >> 32); },
+      [&](int o, int i) -> bool {
+        const uint32_t ko = key[o], ki = key[i];
+        return ko < ki || (ko == ki && o < i);
+      },
+      M.slotbuf);
+  for (int q = t; q < ns; q += TPC) out[q] = (uint16_t)(out[q] + off);
+  __syncthreads();
+}
+
+// Correction order of one species (Alg. 1, optional step): the shuffled list
+// L stably sorted by descending weight.  O receives cell-local indices.
+template <int TPC, int PPT, bool G>
+__device__ __forceinline__ void weight_order(const CellMem &M, int ns, const uint16_t *L,
+                                             uint16_t *O, uint64_t lo, uint64_t hi,
+                                             uint32_t *wsum, uint32_t *maxocc) {
+  const int t = threadIdx.x;
+  if (lo == hi) {  // all weights equal: the shuffled order itself
+    for (int q = t; q < ns; q += TPC) O[q] = L[q];
+    __syncthreads();
+    return;
+  }
+  const double scale = (double)ns / ((double)(hi - lo) + 1.0);
+  const double *w = M.w;
+  auto before = [&](int o, int q) -> bool {
+    const double wo = w[L[o]], wq = w[L[q]];
+    return wo > wq || (wo == wq && o < q);
+  };
+  const uint32_t occ = bucket_rank_sort<TPC, PPT, G>(
+      ns, M.cnt, M.mem, O, wsum, maxocc,
+      [&](int q) -> uint32_t {
+        const uint64_t b = (uint64_t)__double_as_longlong(w[L[q]]);
+        const uint32_t k = (uint32_t)((double)(hi - b) * scale);
+        return k < (uint32_t)ns ? k : (uint32_t)(ns - 1);
+      },
+      before, M.slotbuf);
+  if (occ > 48) {
+    // few distinct weights: the comparison count per bucket grows as its
+    // occupancy squared; a bitonic network is cheaper here
+    int P = 1;
+    while (P < ns) P <<= 1;
+    for (int i = t; i < P; i += TPC) M.mem[i] = i < ns ? (uint16_t)i : (uint16_t)0xFFFF;
+    __syncthreads();
+    bitonic_sort_ids<TPC>(M.mem, P, before);
+    for (int q = t; q < ns; q += TPC) O[q] = M.mem[q];
+    __syncthreads();
+  }
+  for (int q = t; q < ns; q += TPC) O[q] = L[O[q]];
+  __syncthreads();
+}
+
+// Owner loop: particle e = threadIdx.x + j*TPC, j < PPT, unrolled when the
+// per-thread count is small.
+template <int TPC, int PPT, bool UNROLL, class F>
+__device__ __forceinline__ void for_owned(int n, F &&f) {
+  if constexpr (UNROLL) {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int e = threadIdx.x + j * TPC;
+      if (e < n) f(j, e);
+    }
+  } else {
+    for (int j = 0; j < PPT; ++j) {
+      const int e = threadIdx.x + j * TPC;
+      if (e >= n) break;
+      f(j, e);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The kernel
+// ---------------------------------------------------------------------------
+template <int TPC, int CAP, typename KR, bool REL, int LAY>
+__global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
+  constexpr int PPT = CAP / TPC;
+  constexpr int NW = TPC / WAVE;
+  constexpr bool GL = LAY == LAYOUT_GLOBAL;
+  constexpr bool BIG = GL;  // snapshot in memory, runtime owner loops
+  static_assert(CAP % TPC == 0 && TPC % WAVE == 0, "bad variant");
+  static_assert(!(REL && LAY == LAYOUT_COMPACT), "REL needs the full pair buffer");
+  static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
+  __shared__ double red[2 * 6 * NW];
+  __shared__ uint32_t wsum[NW];
+  __shared__ uint32_t maxocc;
+  __shared__ int s_so[MCC_MAX_SPECIES + 1];
+  __shared__ int s_bad;
+  __shared__ unsigned long long s_wlo[MCC_MAX_SPECIES], s_whi[MCC_MAX_SPECIES];
+  __shared__ unsigned long long s_st[4];  // pairs, correction pairs, failures, collisions
+  __shared__ double s_sd[2];              // diagnostics maxima
+  __shared__ int s_ncut[2];
+  __shared__ double s_res[2];
+  __shared__ int s_used[2];
+  __shared__ double s_mass[MCC_MAX_SPECIES];
+  __shared__ CollConst s_coll[MCC_MAX_COLLISIONS];
+  // bucket counters stay in LDS in every layout: global atomics complete in
+  // L2, and later plain loads could hit stale L1 lines
+  __shared__ __attribute__((aligned(16))) uint32_t lcnt[CAP + 2];
+
+  CellMem M;
+  double *wdst = nullptr;  // where the load phase copies the weights (LDS layout)
+  M.cnt = lcnt;
+  M.slotbuf = nullptr;
+  M.bx = M.by = M.bz = nullptr;
+  if constexpr (LAY == LAYOUT_LDS) {
+    __shared__ double lv[4 * CAP];
+    __shared__ uint64_t lscr[CAP + 1];
+    __shared__ uint16_t lidx[5 * CAP];
+    M.vx = lv;
+    M.vy = lv + CAP;
+    M.vz = lv + 2 * CAP;
+    wdst = lv + 3 * CAP;
+    M.w = wdst;
+    M.key = reinterpret_cast<uint32_t *>(lscr);
+    M.kbuf = reinterpret_cast<double *>(lscr);
+    M.list0 = lidx;
+    M.list1 = lidx + CAP;
+    M.ord0 = lidx + 2 * CAP;
+    M.ord1 = lidx + 3 * CAP;
+    M.mem = lidx + 4 * CAP;
+  } else if constexpr (LAY == LAYOUT_COMPACT) {
+    __shared__ double lv[3 * CAP];
+    __shared__ __attribute__((aligned(16))) uint16_t lidx[5 * CAP];
+    M.vx = lv;
+    M.vy = lv + CAP;
+    M.vz = lv + 2 * CAP;
+    M.list0 = lidx;
+    M.list1 = lidx + CAP;
+    M.ord0 = lidx + 2 * CAP;
+    M.ord1 = lidx + 3 * CAP;
+    M.mem = lidx + 4 * CAP;
+    // shuffle keys live in ord0/ord1 (dead until the weight order); the pair
+    // energies live in the bucket counters (dead after the weight order)
+    M.key = reinterpret_cast<uint32_t *>(lidx + 2 * CAP);
+    M.kbuf = reinterpret_cast<double *>(lcnt);
+  } else {
+    char *base = A.big_scratch + (uint64_t)blockIdx.x * A.big_stride;
+    double *dv = reinterpret_cast<double *>(base);
+    M.vx = dv;
+    M.vy = dv + CAP;
+    M.vz = dv + 2 * CAP;
+    wdst = dv + 3 * CAP;
+    M.w = wdst;
+    M.bx = dv + 4 * CAP;
+    M.by = dv + 5 * CAP;
+    M.bz = dv + 6 * CAP;
+    M.kbuf = dv + 7 * CAP;                                       // CAP doubles
+    M.key = reinterpret_cast<uint32_t *>(dv + 8 * CAP);          // CAP u32
+    M.slotbuf = M.key + CAP;                                     // CAP u32
+    uint16_t *ix = reinterpret_cast<uint16_t *>(M.slotbuf + CAP);
+    M.list0 = ix;
+    M.list1 = ix + CAP;
+    M.ord0 = ix + 2 * CAP;
+    M.ord1 = ix + 3 * CAP;
+    M.mem = ix + 4 * CAP;
+  }
+
+  const int t = threadIdx.x;
+  const int S = A.S;
+  const uint64_t step = A.step_dev ? *A.step_dev : A.step;
+  const uint32_t step_lo = (uint32_t)step;
+  const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
+  const uint32_t count = *A.cell_count;
+  // per-species and per-collision constants in LDS (indexed at run time)
+  if (t < MCC_MAX_SPECIES) s_mass[t] = A.mass[t];
+  if (t < MCC_MAX_COLLISIONS) s_coll[t] = A.coll[t];
+  __syncthreads();
+
+  for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
+    const int cell = A.cell_list[li];
+    // cell header: segment offsets, validated once
+    if (t == 0) {
+      const int64_t cb = A.offsets[(int64_t)cell * S];
+      const int64_t ce = A.offsets[(int64_t)(cell + 1) * S];
+      int bad = (cb >= 0 && ce >= cb && ce <= A.n) ? 0 : 1;
+      for (int s = 0; s < S; ++s) {
+        const int64_t o = A.offsets[(int64_t)cell * S + s];
+        const int64_t o1 = A.offsets[(int64_t)cell * S + s + 1];
+        if (o < cb || o1 < o || o1 > ce) bad = 1;
+        s_so[s] = (int)(o - cb);
+      }
+      s_so[S] = (int)(ce - cb);
+      if (!bad && ce - cb > CAP) bad = 2;
+      if (bad) atomicCAS(A.err, 0, bad);
+      s_bad = bad;
+      for (int q = 0; q < 4; ++q) s_st[q] = 0ull;
+      s_sd[0] = s_sd[1] = 0.0;
+    }
+    if (t < MCC_MAX_SPECIES) {
+      s_wlo[t] = ~0ull;
+      s_whi[t] = 0ull;
+    }
+    __syncthreads();
+    if (s_bad) {
+      __syncthreads();
+      continue;  // uniform over the workgroup
+    }
+    const int64_t cb = A.offsets[(int64_t)cell * S];
+    const int n = s_so[S];
+    const double dV = A.cell_volume ? A.cell_volume[cell] : A.dV;
+    if constexpr (LAY == LAYOUT_COMPACT) M.w = A.w + cb;
+
+    for (int e = t; e < n; e += TPC) {
+      M.vx[e] = A.vx[cb + e];
+      M.vy[e] = A.vy[cb + e];
+      M.vz[e] = A.vz[cb + e];
+      const double we = A.w[cb + e];
+      if constexpr (LAY != LAYOUT_COMPACT) wdst[e] = we;
+      if (A.corr && A.sortw) {  // weight range per species (descending-weight order)
+        int s = 0;
+        while (s + 1 < S && e >= s_so[s + 1]) ++s;
+        const unsigned long long bits = (unsigned long long)__double_as_longlong(we);
+        atomicMin(&s_wlo[s], bits);
+        atomicMax(&s_whi[s], bits);
+      }
+    }
+    __syncthreads();
+
+    for (int k = 0; k < A.n_coll; ++k) {
+      const CollConst &C = s_coll[k];
+      const int a = C.a, b = C.b;
+      const bool intra = a == b;
+      const int oa = s_so[a], na = s_so[a + 1] - oa;
+      const int ob = s_so[b], nb = s_so[b + 1] - ob;
+      if (intra ? (na < 2) : (na == 0 || nb == 0)) continue;
+      const double ma = s_mass[a], mb = s_mass[b];
+
+      // pre-scatter snapshot (Alg. 1, first step)
+      double bx[GL ? 1 : PPT], by[GL ? 1 : PPT], bz[GL ? 1 : PPT];
+      for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
+                if (e < n) {
+          if constexpr (BIG) {
+            M.bx[e] = M.vx[e];
+            M.by[e] = M.vy[e];
+            M.bz[e] = M.vz[e];
+          } else {
+            bx[j] = M.vx[e];
+            by[j] = M.vy[e];
+            bz[j] = M.vz[e];
+          }
+        }
+      });
+#define SNAPX(j, e) (BIG ? M.bx[e] : bx[BIG ? 0 : (j)])
+#define SNAPY(j, e) (BIG ? M.by[e] : by[BIG ? 0 : (j)])
+#define SNAPZ(j, e) (BIG ? M.bz[e] : bz[BIG ? 0 : (j)])
+
+      // random binary pairs (Fig. 1)
+      shuffle_species<TPC, PPT, GL>(M, na, oa, (uint32_t)cell, step_lo,
+                                ctr3(step, k, PURPOSE_SHUFFLE0 + 0), k0, k1, M.list0, wsum,
+                                &maxocc);
+      if (!intra)
+        shuffle_species<TPC, PPT, GL>(M, nb, ob, (uint32_t)cell, step_lo,
+                                  ctr3(step, k, PURPOSE_SHUFFLE0 + 1), k0, k1, M.list1, wsum,
+                                  &maxocc);
+
+      // scatter (Sec. 3.2 pairing) in rounds of disjoint pairs:
+      //  intra, even N: one round (L0,L1),(L2,L3),...
+      //  intra, odd N : the triple (L0,L1),(L1,L2),(L2,L0) at s/2 in three
+      //                 rounds; the regular pairs (L3,L4),... in round 0
+      //  inter        : pair k = (big[k], small[k mod N_min]) in rounds of N_min
+      const uint32_t c3p = ctr3(step, k, PURPOSE_PAIR);
+      const bool abig = na >= nb;
+      const int Nmax = abig ? na : nb, Nmin = abig ? nb : na;
+      const double nmin = intra ? (double)(na - 1) : (double)Nmin;
+      const bool odd = intra && (na & 1);
+      const int nrounds = intra ? (odd ? 3 : 1) : (Nmax + Nmin - 1) / Nmin;
+      for (int r = 0; r < nrounds; ++r) {
+        int nslots;
+        if (intra)
+          nslots = odd ? (r == 0 ? 1 + (na - 3) / 2 : 1) : na / 2;
+        else
+          nslots = (Nmax - r * Nmin) < Nmin ? (Nmax - r * Nmin) : Nmin;
+        for (int sl = t; sl < nslots; sl += TPC) {
+          int I, J;
+          uint32_t kp;
+          double f = 1.0;
+          if (intra) {
+            const uint16_t *L = M.list0;
+            if (odd) {
+              if (sl == 0) {
+                I = L[r];
+                J = L[r == 2 ? 0 : r + 1];
+                kp = (uint32_t)r;
+                f = 0.5;
+              } else {
+                const int m = sl - 1;
+                I = L[3 + 2 * m];
+                J = L[4 + 2 * m];
+                kp = (uint32_t)(3 + m);
+              }
+            } else {
+              I = L[2 * sl];
+              J = L[2 * sl + 1];
+              kp = (uint32_t)sl;
+            }
+          } else {
+            const int kk = r * Nmin + sl;
+            I = abig ? M.list0[kk] : M.list0[sl];
+            J = abig ? M.list1[sl] : M.list1[kk];
+            kp = (uint32_t)kk;
+          }
+          const double cf = C.coef * f * (nmin / dV);
+          if constexpr (REL)
+            scatter_pair_rel(M, I, J, kp, cf, ma, mb, A.c, A.method, (uint32_t)cell, step_lo,
+                             c3p, k0, k1);
+          else
+            scatter_pair_nr<KR>(M, I, J, kp, cf, C, A.method, (uint32_t)cell, step_lo, c3p, k0,
+                                k1);
+        }
+        __syncthreads();
+      }
+      if (t == 0) {
+        s_st[0] += intra ? (odd ? 3 + (na - 3) / 2 : na / 2) : Nmax;
+        s_st[3] += 1;
+      }
+
+      if (!A.corr) continue;
+
+      auto part = [&](int e) {
+        return (e >= oa && e < oa + na) || (!intra && e >= ob && e < ob + nb);
+      };
+      auto mass_of = [&](int e) { return (e >= oa && e < oa + na) ? ma : mb; };
+
+      // momentum restore, Eq. (17): B = sum m_p (v_ps - v_bs) / sum m_p w_p
+      {
+        CSum<4> P;
+        P.zero();
+        for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
+                    if (e < n && part(e)) {
+            const double mp = mass_of(e) * M.w[e];
+            P.add(0, mp * (M.vx[e] - SNAPX(j, e)));
+            P.add(1, mp * (M.vy[e] - SNAPY(j, e)));
+            P.add(2, mp * (M.vz[e] - SNAPZ(j, e)));
+            P.add(3, mp * M.w[e]);
+          }
+        });
+        double tot[4];
+        block_csum<TPC, 4>(P, red, tot);
+        const double Bx = tot[0] / tot[3], By = tot[1] / tot[3], Bz = tot[2] / tot[3];
+        for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
+                    if (e < n && part(e)) {
+            const double we = M.w[e];
+            M.vx[e] -= Bx * we;
+            M.vy[e] -= By * we;
+            M.vz[e] -= Bz * we;
+          }
+        });
+      }
+      // energy violation, Eq. (18) (difference form), and the sums of Eq. (24)
+      double dEs0, dEs1;
+      {
+        CSum<5> E;
+        E.zero();
+        const double c2 = A.c * A.c;
+        for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
+                    if (e < n && part(e)) {
+            const bool isa = e >= oa && e < oa + na;
+            const double mp = (isa ? ma : mb) * M.w[e];
+            const double vx = M.vx[e], vy = M.vy[e], vz = M.vz[e];
+            const double ox = SNAPX(j, e), oy = SNAPY(j, e), oz = SNAPZ(j, e);
+            const double dd = (vx - ox) * (vx + ox) + (vy - oy) * (vy + oy) + (vz - oz) * (vz + oz);
+            const double vv = vx * vx + vy * vy + vz * vz;
+            double term, ke;
+            if constexpr (REL) {
+              const double gv = sqrt(1.0 + vv / c2);
+              const double gb = sqrt(1.0 + (ox * ox + oy * oy + oz * oz) / c2);
+              term = mp * dd / (gv + gb);
+              ke = mp * vv / (gv + 1.0);
+            } else {
+              term = 0.5 * mp * dd;
+              ke = 0.5 * mp * vv;
+            }
+            E.add(0, term);
+            if (isa) {
+              E.add(1, ke);
+              E.add(3, M.w[e]);
+            } else {
+              E.add(2, ke);
+              E.add(4, M.w[e]);
+            }
+          }
+        });
+        double tot[5];
+        block_csum<TPC, 5>(E, red, tot);
+        dEs0 = tot[0];
+        dEs1 = 0.0;
+        if (!intra && tot[0] != 0.0) {
+          const double ea = tot[3] / na * tot[1], eb = tot[4] / nb * tot[2];
+          dEs0 = ea / (ea + eb) * tot[0];
+          dEs1 = eb / (ea + eb) * tot[0];
+        }
+      }
+
+      // correction order per species (Alg. 1, optional sort), then the pair loop
+      const int nsl = intra ? 1 : 2;
+      uint16_t *O0 = M.list0, *O1 = M.list1;
+      if (A.sortw) {
+        weight_order<TPC, PPT, GL>(M, na, M.list0, M.ord0, s_wlo[a], s_whi[a], wsum, &maxocc);
+        O0 = M.ord0;
+        if (!intra) {
+          weight_order<TPC, PPT, GL>(M, nb, M.list1, M.ord1, s_wlo[b], s_whi[b], wsum, &maxocc);
+          O1 = M.ord1;
+        }
+      }
+      double *Kb = M.kbuf;
+      const int base1 = na / 2;           // pair slots of the second species
+      double *Xb = Kb + CAP / 2;          // REL: h(-mu_R) per pair
+      double resid0 = dEs0, resid1 = dEs1;
+      int used_total = 0;
+      for (int pass = 0; pass < A.max_passes; ++pass) {
+        if (resid0 == 0.0 && resid1 == 0.0) break;
+        // K of every pair; pairs are disjoint, so each K is the value the
+        // sequential loop of Alg. 1 sees
+        const int np0 = (resid0 != 0.0) ? na / 2 : 0;
+        const int np1 = (nsl == 2 && resid1 != 0.0) ? nb / 2 : 0;
+        for (int m = t; m < np0 + np1; m += TPC) {
+          const bool s1 = m >= np0;
+          const int mm = s1 ? m - np0 : m;
+          const uint16_t *O = s1 ? O1 : O0;
+          const double ms = s1 ? mb : ma;
+          const int slot = (s1 ? base1 : 0) + mm;
+          const int p = O[2 * mm], q = O[2 * mm + 1];
+          const double m1 = ms * M.w[p], m2 = ms * M.w[q];
+          if constexpr (REL) {
+            Kb[slot] = pair_K_rel(m1, m2, M.vx[p], M.vy[p], M.vz[p], M.vx[q], M.vy[q], M.vz[q],
+                                  A.c);
+            RelPair R;
+            R.init(m1, m2, M.vx[p], M.vy[p], M.vz[p], M.vx[q], M.vy[q], M.vz[q], A.c);
+            double dh;
+            Xb[slot] = R.h0(-R.mu(), dh);
+          } else {
+            Kb[slot] = pair_K_nr(m1, m2, M.vx[p], M.vy[p], M.vz[p], M.vx[q], M.vy[q], M.vz[q]);
+          }
+        }
+        __syncthreads();
+        // the running violation, in the paper's order (one lane per species)
+        {
+          const int sl = (t == 0) ? 0 : ((NW > 1 && t == WAVE) ? 1 : -1);
+          for (int s2 = (NW > 1 ? sl : 0); s2 >= 0 && s2 < nsl; s2 += (NW > 1 ? nsl : 1)) {
+            if (NW == 1 && t != 0) break;
+            double E = s2 == 0 ? resid0 : resid1;
+            const int np = (s2 == 0 ? na : nb) / 2, kb = s2 == 0 ? 0 : base1;
+            int m = 0, used = 0;
+            for (; m < np; ++m) {
+              if (E == 0.0) break;
+              const double K = Kb[kb + m];
+              double U = 0.0;
+              if (K != 0.0) {
+                const double lim = A.fE * K;
+                U = fabs(E) < lim ? E : copysign(lim, E);
+                if constexpr (REL) {
+                  if (U > 0.0 && Xb[kb + m] + U > 0.0) U = 0.0;  // no root: skip the pair
+                }
+              }
+              Kb[kb + m] = U;
+              if (U != 0.0) {
+                E -= U;
+                ++used;
+              }
+            }
+            s_ncut[s2] = m;
+            s_res[s2] = E;
+            s_used[s2] = used;
+          }
+          if (nsl == 1 && t == 0) {
+            s_ncut[1] = 0;
+            s_res[1] = 0.0;
+            s_used[1] = 0;
+          }
+        }
+        __syncthreads();
+        // apply the pair corrections, Eqs. (19)-(22) / (A.3)-(A.5)
+        const int nc0 = s_ncut[0], nc1 = s_ncut[1];
+        for (int m = t; m < nc0 + nc1; m += TPC) {
+          const bool s1 = m >= nc0;
+          const int mm = s1 ? m - nc0 : m;
+          const int slot = (s1 ? base1 : 0) + mm;
+          const double U = Kb[slot];
+          if (U == 0.0) continue;
+          const uint16_t *O = s1 ? O1 : O0;
+          const double ms = s1 ? mb : ma;
+          const int p = O[2 * mm], q = O[2 * mm + 1];
+          const double m1 = ms * M.w[p], m2 = ms * M.w[q];
+          if constexpr (REL) {
+            RelPair R;
+            R.init(m1, m2, M.vx[p], M.vy[p], M.vz[p], M.vx[q], M.vy[q], M.vz[q], A.c);
+            const double al = rel_alpha(R, U);
+            const double f1 = al / m1, f2 = al / m2;
+            M.vx[p] += f1 * R.dx;
+            M.vy[p] += f1 * R.dy;
+            M.vz[p] += f1 * R.dz;
+            M.vx[q] -= f2 * R.dx;
+            M.vy[q] -= f2 * R.dy;
+            M.vz[q] -= f2 * R.dz;
+          } else {
+            const double mu = m1 * m2 / (m1 + m2);
+            const double rx = M.vx[p] - M.vx[q], ry = M.vy[p] - M.vy[q], rz = M.vz[p] - M.vz[q];
+            const double K = 0.5 * mu * (rx * rx + ry * ry + rz * rz);
+            const double x = U / K;
+            const double g = -x / (1.0 + sqrt(1.0 - x));
+            const double f1 = mu / m1 * g, f2 = mu / m2 * g;
+            M.vx[p] += f1 * rx;
+            M.vy[p] += f1 * ry;
+            M.vz[p] += f1 * rz;
+            M.vx[q] -= f2 * rx;
+            M.vy[q] -= f2 * ry;
+            M.vz[q] -= f2 * rz;
+          }
+        }
+        resid0 = s_res[0];
+        resid1 = s_res[1];
+        used_total += s_used[0] + s_used[1];
+        __syncthreads();
+      }
+      const bool failed = resid0 != 0.0 || resid1 != 0.0;
+      if (t == 0) {
+        s_st[1] += used_total;
+        s_st[2] += failed ? 1 : 0;
+      }
+      if (failed && !A.keep) {  // Sec. 6.2: reset this collision in this cell
+        for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
+                    if (e < n && part(e)) {
+            M.vx[e] = SNAPX(j, e);
+            M.vy[e] = SNAPY(j, e);
+            M.vz[e] = SNAPZ(j, e);
+          }
+        });
+      }
+      __syncthreads();
+      if (A.diag) {  // residual momentum and energy of this collision
+        CSum<6> D;
+        D.zero();
+        const double c2 = A.c * A.c;
+        for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
+                    if (e < n && part(e)) {
+            const double mp = mass_of(e) * M.w[e];
+            const double vx = M.vx[e], vy = M.vy[e], vz = M.vz[e];
+            const double ox = SNAPX(j, e), oy = SNAPY(j, e), oz = SNAPZ(j, e);
+            D.add(0, mp * (vx - ox));
+            D.add(1, mp * (vy - oy));
+            D.add(2, mp * (vz - oz));
+            const double oo = ox * ox + oy * oy + oz * oz;
+            D.add(3, mp * sqrt(oo));
+            const double dd = (vx - ox) * (vx + ox) + (vy - oy) * (vy + oy) + (vz - oz) * (vz + oz);
+            if constexpr (REL) {
+              const double gv = sqrt(1.0 + (vx * vx + vy * vy + vz * vz) / c2);
+              const double gb = sqrt(1.0 + oo / c2);
+              D.add(4, mp * dd / (gv + gb));
+              D.add(5, mp * oo / (gb + 1.0));
+            } else {
+              D.add(4, 0.5 * mp * dd);
+              D.add(5, 0.5 * mp * oo);
+            }
+          }
+        });
+        double tot[6];
+        block_csum<TPC, 6>(D, red, tot);
+        if (t == 0) {
+          const double rp = sqrt(tot[0] * tot[0] + tot[1] * tot[1] + tot[2] * tot[2]);
+          const double relP = tot[3] > 0.0 ? rp / tot[3] : 0.0;
+          const double relE = tot[5] > 0.0 ? fabs(tot[4]) / tot[5] : 0.0;
+          s_sd[0] = relP > s_sd[0] ? relP : s_sd[0];
+          s_sd[1] = relE > s_sd[1] ? relE : s_sd[1];
+        }
+      }
+#undef SNAPX
+#undef SNAPY
+#undef SNAPZ
+    }
+
+    __syncthreads();
+    for (int e = t; e < n; e += TPC) {
+      A.vx[cb + e] = M.vx[e];
+      A.vy[cb + e] = M.vy[e];
+      A.vz[cb + e] = M.vz[e];
+    }
+    if (t == 0) {
+      if (A.cell_corr) A.cell_corr[cell] = (int32_t)s_st[1];
+      if (A.stats) {
+        atomicAdd(&A.stats->pairs, s_st[0]);
+        if (s_st[1]) atomicAdd(&A.stats->corr_pairs, s_st[1]);
+        if (s_st[2]) atomicAdd(&A.stats->failed, s_st[2]);
+        atomicAdd(&A.stats->collisions, s_st[3]);
+        if (A.diag) {
+          atomicMax(reinterpret_cast<unsigned long long *>(&A.stats->max_rel_dP),
+                    (unsigned long long)__double_as_longlong(s_sd[0]));
+          atomicMax(reinterpret_cast<unsigned long long *>(&A.stats->max_rel_dE),
+                    (unsigned long long)__double_as_longlong(s_sd[1]));
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace mcc

@@ -1,0 +1,485 @@
+// mcc_device.hpp -- device building blocks for gfx950 (wave64):
+// Philox4x32-10, compensated block reductions, block scans, LDS sorts and
+// the scalar math of the scatter (N97 inversion, angle sampling, rotation).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcc {
+
+constexpr int WAVE = 64;
+constexpr double PI_D = 3.14159265358979323846;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  Counter layout:
+//   c0 = index (pair k, or particle index >> 2 for the shuffle keys)
+//   c1 = global cell id, c2 = step (low 32 bits)
+//   c3 = (step >> 32 & 0xFFFF) << 16 | collision << 8 | purpose
+// ---------------------------------------------------------------------------
+struct U4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2,
+                                     uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return U4{c0, c1, c2, c3};
+}
+
+enum : uint32_t { PURPOSE_PAIR = 0, PURPOSE_SHUFFLE0 = 1 };
+
+__device__ __forceinline__ uint32_t ctr3(uint64_t step, int coll, uint32_t purpose) {
+  return (uint32_t)(((step >> 32) & 0xFFFFu) << 16) | ((uint32_t)(coll & 0xFF) << 8) | purpose;
+}
+
+// uniform in (0,1), exact in FP64
+__device__ __forceinline__ double unif64(uint32_t a) { return ((double)a + 0.5) * 0x1p-32; }
+// uniform in (0,1), exact in FP32 (top 24 bits of the word)
+__device__ __forceinline__ float unif32(uint32_t a) {
+  return ((float)(a >> 8) + 0.5f) * 0x1p-24f;
+}
+
+// ---------------------------------------------------------------------------
+// Error-free transforms and compensated block sums
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// accumulate x into (s, c) Neumaier-style, branch-free via TwoSum
+__device__ __forceinline__ void csum_add(double &s, double &c, double x) {
+  double t, e;
+  two_sum(s, x, t, e);
+  s = t;
+  c += e;
+}
+
+template <int N>
+struct CSum {
+  double s[N], c[N];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < N; ++i) s[i] = c[i] = 0.0;
+  }
+  __device__ __forceinline__ void add(int i, double x) { csum_add(s[i], c[i], x); }
+};
+
+// Sum of N compensated values over the block; every thread receives the
+// totals.  `red` is LDS scratch of at least 2*N*(TPC/64) doubles.  Ends with a
+// barrier so `red` may be reused right after.
+template <int TPC, int N, bool G = false>
+__device__ __forceinline__ void block_csum(CSum<N> &v, double *red, double out[N]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  constexpr int NW = TPC / WAVE;
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const double s2 = __shfl_xor(v.s[i], off);
+      const double c2 = __shfl_xor(v.c[i], off);
+      double t, e;
+      two_sum(v.s[i], s2, t, e);
+      v.s[i] = t;
+      v.c[i] = v.c[i] + c2 + e;
+    }
+  }
+  if (NW == 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = v.s[i] + v.c[i];
+    __syncthreads();
+    return;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      red[(wid * N + i) * 2] = v.s[i];
+      red[(wid * N + i) * 2 + 1] = v.c[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double s = red[i * 2], c = red[i * 2 + 1];
+    for (int w = 1; w < NW; ++w) {
+      double t, e;
+      two_sum(s, red[(w * N + i) * 2], t, e);
+      s = t;
+      c = c + red[(w * N + i) * 2 + 1] + e;
+    }
+    out[i] = s + c;
+  }
+  __syncthreads();
+}
+
+// min and max of N u64 values over the block (all threads receive them)
+template <int TPC, int N, bool G = false>
+__device__ __forceinline__ void block_minmax_u64(uint64_t lo[N], uint64_t hi[N], uint64_t *red) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  constexpr int NW = TPC / WAVE;
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const uint64_t a = __shfl_xor(lo[i], off);
+      const uint64_t b = __shfl_xor(hi[i], off);
+      lo[i] = a < lo[i] ? a : lo[i];
+      hi[i] = b > hi[i] ? b : hi[i];
+    }
+  }
+  if (NW == 1) {
+    __syncthreads();
+    return;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      red[(wid * N + i) * 2] = lo[i];
+      red[(wid * N + i) * 2 + 1] = hi[i];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    uint64_t a = red[i * 2], b = red[i * 2 + 1];
+    for (int w = 1; w < NW; ++w) {
+      const uint64_t x = red[(w * N + i) * 2], y = red[(w * N + i) * 2 + 1];
+      a = x < a ? x : a;
+      b = y > b ? y : b;
+    }
+    lo[i] = a;
+    hi[i] = b;
+  }
+  __syncthreads();
+}
+
+// In-place exclusive scan of a[0..n) (n <= TPC*PPT); a[n] receives the total.
+// Thread t owns the chunk [t*PPT, t*PPT + PPT).  wsum: TPC/64 u32 of LDS.
+// Ends with a barrier.
+template <int TPC, int PPT, bool G = false>
+__device__ __forceinline__ void block_exclusive_scan(uint32_t *a, int n, uint32_t *wsum) {
+  const int t = threadIdx.x;
+  const int lane = t & (WAVE - 1);
+  const int wid = t / WAVE;
+  constexpr int NW = TPC / WAVE;
+  const int lo = t * PPT, hi = (lo + PPT < n) ? lo + PPT : n;
+  uint32_t tot = 0;
+  for (int idx = lo; idx < hi; ++idx) tot += a[idx];
+  uint32_t incl = tot;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t y = __shfl_up(incl, d);
+    if (lane >= d) incl += y;
+  }
+  if (lane == WAVE - 1) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t woff = 0, total = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t x = wsum[w];
+    if (w < wid) woff += x;
+    total += x;
+  }
+  uint32_t ex = woff + incl - tot;
+  for (int idx = lo; idx < hi; ++idx) {
+    const uint32_t x = a[idx];
+    a[idx] = ex;
+    ex += x;
+  }
+  if (t == 0) a[n] = total;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Bucket-rank sort in LDS.  Items 0..n-1 (n <= CAP) with a bucket function
+// that is non-decreasing in the sort order and a strict total order `less`.
+// out[pos] = item.  The result equals a full sort by `less`; the bucket only
+// decides how much comparing is needed (about one item per bucket for
+// uniform keys).  cnt: u32[CAP+1]; mem: u16[CAP]; wsum: TPC/64 u32.
+// Returns the largest bucket occupancy (all threads).
+// ---------------------------------------------------------------------------
+template <int TPC, int PPT, bool G, class BucketF, class LessF>
+__device__ __forceinline__ uint32_t bucket_rank_sort(int n, uint32_t *cnt, uint16_t *mem,
+                                                    uint16_t *out, uint32_t *wsum,
+                                                    uint32_t *maxocc, BucketF bucket,
+                                                    LessF less, uint32_t *slotbuf = nullptr) {
+  // G: many items per thread; the per-item slot goes to slotbuf[] (memory
+  // private to the item's thread) instead of registers, and the bucket is
+  // recomputed instead of kept
+  const int t = threadIdx.x;
+  constexpr int R = G ? 1 : PPT;
+  for (int i = t; i < n; i += TPC) cnt[i] = 0u;
+  if (t == 0) *maxocc = 0u;
+  __syncthreads();
+  uint32_t bk[R], slot[R];
+  uint32_t mo = 0;
+  if constexpr (G) {
+    for (int i = t; i < n; i += TPC) {
+      const uint32_t s0 = atomicAdd(&cnt[bucket(i)], 1u);
+      slotbuf[i] = s0;
+      mo = s0 + 1 > mo ? s0 + 1 : mo;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int i = t + j * TPC;
+      if (i < n) {
+        bk[j] = bucket(i);
+        slot[j] = atomicAdd(&cnt[bk[j]], 1u);
+        mo = slot[j] + 1 > mo ? slot[j] + 1 : mo;
+      }
+    }
+  }
+  __syncthreads();
+  if (mo > 1) atomicMax(maxocc, mo);
+  block_exclusive_scan<TPC, PPT, G>(cnt, n, wsum);
+  // read here, between barriers: the next call resets *maxocc only after this
+  // call's last barrier, so every thread returns the same value
+  const uint32_t occ = *maxocc;
+  if constexpr (G) {
+    for (int i = t; i < n; i += TPC) mem[cnt[bucket(i)] + slotbuf[i]] = (uint16_t)i;
+  } else {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int i = t + j * TPC;
+      if (i < n) mem[cnt[bk[j]] + slot[j]] = (uint16_t)i;
+    }
+  }
+  __syncthreads();
+  auto place = [&](int i, uint32_t b) {
+    const uint32_t s0 = cnt[b], s1 = cnt[b + 1];
+    uint32_t r = 0;
+    for (uint32_t m = s0; m < s1; ++m) {
+      const int o = mem[m];
+      if (o != i && less(o, i)) ++r;
+    }
+    out[s0 + r] = (uint16_t)i;
+  };
+  if constexpr (G) {
+    for (int i = t; i < n; i += TPC) place(i, bucket(i));
+  } else {
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int i = t + j * TPC;
+      if (i < n) place(i, bk[j]);
+    }
+  }
+  __syncthreads();
+  return occ;
+}
+
+// Bitonic sort of P = 2^k item ids in LDS under a strict total order
+// `less(a, b)`; padding entries hold 0xFFFF and sort last.
+template <int TPC, class LessF>
+__device__ __forceinline__ void bitonic_sort_ids(uint16_t *val, int P, LessF less) {
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += TPC) {
+        const int p = i ^ j;
+        if (p > i) {
+          const bool up = (i & k) == 0;
+          const uint16_t vi = val[i], vp = val[p];
+          // greater(vi, vp): padding is the largest
+          const bool gt = (vi == 0xFFFF) ? (vp != 0xFFFF) : (vp != 0xFFFF && less(vp, vi));
+          if (gt == up) {
+            val[i] = vp;
+            val[p] = vi;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Scalar math of the pair scatter, templated on the kinematics type.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct KMath;
+
+template <>
+struct KMath<double> {
+  static __device__ __forceinline__ double u(uint32_t a) { return unif64(a); }
+  static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double log_(double x) { return log(x); }
+  static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+  static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+  static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
+  static __device__ __forceinline__ double sinh_(double x) { return sinh(x); }
+  // sin and cos of 2 pi x
+  static __device__ __forceinline__ void sincos2pi(double x, double &s, double &c) {
+    sincospi(2.0 * x, &s, &c);
+  }
+  static __device__ __forceinline__ double cos2pi(double x) { return cospi(2.0 * x); }
+  static constexpr int NEWTON_MAX = 60;
+  static constexpr double EPS = 2.220446049250313e-16;
+  static constexpr double S_ISO = 50.0;
+};
+
+template <>
+struct KMath<float> {
+  static __device__ __forceinline__ float u(uint32_t a) { return unif32(a); }
+  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+  static __device__ __forceinline__ float log_(float x) {
+    return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
+  }
+  static __device__ __forceinline__ float exp_(float x) {
+    return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+  }
+  static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+  static __device__ __forceinline__ float log1p_(float x) { return log1pf(x); }
+  static __device__ __forceinline__ float sinh_(float x) { return sinhf(x); }
+  // v_sin_f32 / v_cos_f32 take their argument in revolutions
+  static __device__ __forceinline__ void sincos2pi(float x, float &s, float &c) {
+    s = __builtin_amdgcn_sinf(x);
+    c = __builtin_amdgcn_cosf(x);
+  }
+  static __device__ __forceinline__ float cos2pi(float x) { return __builtin_amdgcn_cosf(x); }
+  static constexpr int NEWTON_MAX = 12;
+  static constexpr float EPS = 1.1920929e-7f;
+  static constexpr float S_ISO = 24.0f;
+};
+
+// coth A - 1/A for A < 1/2 by its continued fraction
+// x/(3 + x^2/(5 + x^2/(7 + ...))), depth chosen for the type
+template <typename T>
+__device__ __forceinline__ T langevin_small(T A) {
+  const T x2 = A * A;
+  constexpr int D = sizeof(T) == 8 ? 12 : 6;
+  T d = T(2 * D + 3);
+#pragma unroll
+  for (int k = D; k >= 1; --k) d = T(2 * k + 1) + x2 / d;
+  return A / d;
+}
+
+template <typename T>
+__device__ __forceinline__ T langevin_deriv(T A) {
+  using M = KMath<T>;
+  if (A < T(0.5)) {
+    const T x2 = A * A;
+    return T(1) / T(3) - x2 / T(15) + T(2) * x2 * x2 / T(189) - x2 * x2 * x2 / T(675);
+  }
+  const T sh = M::sinh_(A);
+  return T(1) / (A * A) - T(1) / (sh * sh);
+}
+
+// Nanbu's A(s): coth A - 1/A = exp(-s).  For s <= ln 2 the equation is
+// solved for 1 - L(A) = -expm1(-s); otherwise for L(A) = exp(-s).  Newton
+// inside a bracket.  Returns +inf for s == 0 and 0 when exp(-s) underflows.
+template <typename T>
+__device__ T n97_A(T s) {
+  using M = KMath<T>;
+  if (!(s > T(0))) return T(__builtin_inf());
+  // large s: A = 3 e^{-s} is below the type's resolution relative to 1 and
+  // the sampled angle is isotropic to rounding; avoids subnormal A
+  if (s > M::S_ISO) return T(0);
+  const bool useM = s <= T(0.69314718055994531);
+  T target, lo = T(0), hi, A;
+  if (useM) {
+    target = -M::expm1_(-s);
+    hi = T(1) / target;
+    A = hi;
+  } else {
+    target = M::exp_(-s);
+    if (target == T(0)) return T(0);
+    hi = T(1) / (T(1) - target);
+    A = T(3) * target;
+    if (A >= hi) A = T(0.5) * hi;
+  }
+  for (int it = 0; it < M::NEWTON_MAX; ++it) {
+    T g;
+    if (useM) {
+      const T m = A < T(0.5) ? T(1) - langevin_small(A) : T(1) / A - T(2) / M::expm1_(T(2) * A);
+      g = target - m;
+    } else {
+      const T l = A < T(0.5) ? langevin_small(A) : T(1) + T(2) / M::expm1_(T(2) * A) - T(1) / A;
+      g = l - target;
+    }
+    if (g == T(0)) break;
+    if (g < T(0))
+      lo = A;
+    else
+      hi = A;
+    if (hi - lo <= T(4) * M::EPS * hi) break;
+    T An = A - g / langevin_deriv(A);
+    if (!(An > lo && An < hi)) An = T(0.5) * (lo + hi);
+    if (fabs(An - A) <= T(0.5) * M::EPS * A) {
+      A = An;
+      break;
+    }
+    A = An;
+  }
+  return A;
+}
+
+// Sampled polar angle: oc = 1 - cos(theta), st = sin(theta).
+template <typename T>
+__device__ __forceinline__ void sample_angle(int method, T s, uint32_t a0, uint32_t a1, T &oc,
+                                             T &st) {
+  using M = KMath<T>;
+  const T u0 = M::u(a0);
+  if (method == 0) {  // TA77: tan(theta/2) ~ N(0, s/2)
+    const T z = M::sqrt_(T(-2) * M::log_(u0)) * M::cos2pi(M::u(a1));
+    const T delta = M::sqrt_(T(0.5) * s) * z;
+    const T d2 = delta * delta;
+    if (__builtin_isinf(d2)) {
+      oc = T(2);
+      st = T(0);
+    } else {
+      const T q = T(1) / (T(1) + d2);
+      st = T(2) * delta * q;
+      oc = T(2) * d2 * q;
+    }
+  } else {  // N97
+    const T A = n97_A<T>(s);
+    if (__builtin_isinf(A))
+      oc = T(0);
+    else if (A == T(0))
+      oc = T(2) * u0;
+    else
+      oc = -M::log1p_(u0 * M::expm1_(T(-2) * A)) / A;
+    oc = oc < T(0) ? T(0) : (oc > T(2) ? T(2) : oc);
+    st = M::sqrt_(oc * (T(2) - oc));
+  }
+}
+
+// change of u under rotation by theta about u, azimuth phi (TA77 form)
+template <typename T>
+__device__ __forceinline__ void rotate_delta(T ux, T uy, T uz, T st, T oc, T sp, T cp, T &dx,
+                                             T &dy, T &dz) {
+  using M = KMath<T>;
+  const T up2 = ux * ux + uy * uy;
+  const T up = M::sqrt_(up2);
+  const T um = M::sqrt_(up2 + uz * uz);
+  if (up > T(0)) {
+    const T ax = ux / up, ay = uy / up;
+    dx = ax * uz * st * cp - ay * um * st * sp - ux * oc;
+    dy = ay * uz * st * cp + ax * um * st * sp - uy * oc;
+    dz = -up * st * cp - uz * oc;
+  } else {
+    dx = um * st * cp;
+    dy = um * st * sp;
+    dz = -uz * oc;
+  }
+}
+
+}  // namespace mcc

@@ -1,0 +1,41 @@
+// mcc_kernel_args.hpp -- argument block shared by the host launcher and the
+// collide kernels (passed by value, one kernel argument).
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/mcc.h"
+
+namespace mcc {
+
+// Per-collision constants computed on the host in FP64.
+struct CollConst {
+  int32_t a, b;   // species of the collision (a == b: intra-species)
+  double coef;    // NR: qa^2 qb^2 lnL dt / (4 pi eps0^2 mu^2); REL: without mu^2
+  double fa, fb;  // m_b/(m_a+m_b), m_a/(m_a+m_b): shares of du (Eq. (8) masses)
+};
+
+struct CollideArgs {
+  const int64_t *offsets;  // [n_cells*S + 1]
+  const double *w;
+  double *vx, *vy, *vz;
+  const double *cell_volume;  // nullable
+  double dV;
+  int64_t n;
+  int32_t n_cells, S, n_coll;
+  int32_t method, corr, sortw, max_passes, keep, diag;
+  double fE, c;
+  uint64_t seed, step;
+  const uint64_t *step_dev;  // nullable: step read from device memory (graph replay)
+  double mass[MCC_MAX_SPECIES];
+  CollConst coll[MCC_MAX_COLLISIONS];
+  const int32_t *cell_list;     // work list of this size bucket
+  const uint32_t *cell_count;   // device count of cell_list
+  mcc_stats *stats;             // nullable
+  int32_t *cell_corr;           // nullable
+  int32_t *err;                 // device error word
+  char *big_scratch;            // large-cell variants: per-block global scratch
+  uint64_t big_stride;          // bytes per block
+};
+
+}  // namespace mcc

@@ -1,0 +1,50 @@
+// mcc_variants.hpp -- kernel variants (threads per cell, cell capacity) and
+// the cell-size buckets they serve.  Shared by the host runtime and the
+// instantiation units.
+#pragma once
+
+namespace mcc {
+
+// precision / physics modes compiled
+enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_REL = 2, NMODE = 3 };
+
+// layout: 0 all in LDS; 1 compact LDS (weights read from the input);
+// 2 per-workgroup global scratch with one wave per cell
+struct Variant {
+  int tpc;     // threads per cell (workgroup size)
+  int cap;     // largest cell the variant holds
+  int layout;  // 0 LDS, 1 compact LDS, 2 global scratch
+};
+
+constexpr int NVARIANT = 11;
+constexpr Variant kVariants[NVARIANT] = {
+    {64, 128, 0},   {64, 256, 0},   {128, 256, 0},   {128, 512, 0},
+    {256, 512, 0},  {256, 1024, 0}, {512, 1024, 0},  {512, 2048, 0},
+    {1024, 2048, 0}, {1024, 4096, 1}, {64, 32768, 2}};
+// the relativistic mode keeps a per-pair h(-mu) buffer, which the compact
+// layout has no room for: its 4096-cell variant uses global scratch
+constexpr Variant kRelVariant9 = {64, 4096, 2};
+
+// cell-size buckets: bucket b holds cells with kBucketCap[b-1] < n <= kBucketCap[b]
+constexpr int NBUCKET = 7;
+constexpr int kBucketCap[NBUCKET] = {128, 256, 512, 1024, 2048, 4096, 32768};
+// default variant per bucket (the autotuner may pick another candidate)
+constexpr int kDefaultVariant[NBUCKET] = {0, 2, 4, 6, 8, 9, 10};
+// candidates the autotuner times per bucket (-1 terminated)
+constexpr int kCandidates[NBUCKET][5] = {
+    {0, 1, 2, -1, -1}, {1, 2, 3, 4, -1}, {3, 4, 5, 6, -1}, {5, 6, 7, 8, -1},
+    {7, 8, -1, -1, -1}, {9, -1, -1, -1, -1}, {10, -1, -1, -1, -1}};
+
+
+inline constexpr Variant variant_of(int mode, int v) {
+  return (mode == MODE_REL && v == 9) ? kRelVariant9 : kVariants[v];
+}
+
+// global scratch bytes per workgroup of a global-layout variant:
+// 8 CAP doubles (v, w, snapshot, pair buffer), 2 CAP u32 (keys, slots),
+// 5 CAP u16 (lists, orders, bucket members)
+constexpr unsigned long long big_stride_bytes(int cap) {
+  return ((unsigned long long)cap * (8 * 8 + 2 * 4 + 5 * 2) + 255ull) & ~255ull;
+}
+
+}  // namespace mcc

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP library against the CPU FP64 oracle on the same seeded
+inputs and the same Philox draws, called through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_19151_amd import workloads as W
+
+from gpu_helpers import FP64_TOL, check_parity, custom_workload, oracle_step, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_19151_amd import native
+    c = native.Context()
+    yield c
+    c.close()
+
+
+def _gpu_step(ctx, wl, step, **pover):
+    from paper_2407_19151_amd import native, runner
+    dw = runner.DeviceWorkload(wl)
+    runner.collide_sorted(ctx, dw, step, params=runner.params_for(wl, **pover))
+    v = dw.velocities()
+    st = native.read_stats(dw.stats)
+    cc = dw.cell_corr.cpu().numpy()
+    assert ctx.device_error() == 0
+    return v, st, cc
+
+
+def _parity(ctx, wl, step=0, tol=FP64_TOL, counts_exact=True, **over):
+    v0 = wl.velocities().copy()
+    print("parity case: %s cells=%d n=%d step=%d %s" % (wl.name, wl.n_cells, wl.n, step, over),
+          flush=True)
+    vg, sg, cg = _gpu_step(ctx, wl, step, **over)
+    ref = wl.copy()
+    oover = {k: v for k, v in over.items() if k not in ("precision", "diagnostics")}
+    if "on_failure" in oover:
+        oover["keep_on_fail"] = oover.pop("on_failure") == 1
+    if "moment_correction" in oover:
+        oover["correction"] = oover.pop("moment_correction")
+    so = oracle_step(ref, step, **oover)
+    vr = ref.velocities()
+    info = check_parity(wl, vg, vr, v0, tol=tol)
+    print("  parity:", info, flush=True)
+    assert sg["pairs"] == so["pairs"]
+    assert sg["collisions"] == so["collisions"]
+    if counts_exact:
+        assert sg["failed"] == so["failed"]
+        assert abs(int(sg["corr_pairs"]) - so["corr_pairs"]) <= max(1, so["corr_pairs"] // 1000)
+        assert np.mean(cg == so["cell_corr_pairs"]) >= 0.99
+    return info, sg, so
+
+
+@pytest.mark.parametrize("method", [W.N97, W.TA77])
+def test_parity_config1_one_species_lognormal(ctx, method):
+    wl = W.config1(method=method)
+    for step in (0, 7):
+        _parity(ctx, wl.copy(), step)
+
+
+@pytest.mark.parametrize("method", [W.N97, W.TA77])
+def test_parity_config2_subset_two_species(ctx, method):
+    wl = W.config2(n_cells=48, method=method)
+    _parity(ctx, wl, 3)
+
+
+def test_parity_every_bucket_and_ragged_edges(ctx):
+    """Cells spanning every size bucket and variant (LDS and global
+    scratch), odd and even counts, empty species, single particles, N_min = 1."""
+    sizes = [(0, 0), (1, 0), (0, 1), (1, 1), (2, 0), (3, 0), (2, 1), (1, 5), (5, 1), (3, 3),
+             (7, 9), (64, 63), (65, 64), (100, 27), (129, 128), (200, 55), (255, 256),
+             (300, 211), (511, 512), (700, 300), (1000, 1), (1023, 1024), (1500, 547),
+             (2047, 2048), (2500, 1500), (1, 3000)]
+    wl = custom_workload(sizes, seed=4)
+    _parity(ctx, wl, 1)
+
+
+def test_parity_large_global_scratch_cells(ctx):
+    sizes = [(3000, 1095), (5000, 4000), (100, 16000)]
+    wl = custom_workload(sizes, seed=5)
+    _parity(ctx, wl, 2)
+
+
+@pytest.mark.parametrize("wmode", ["lognormal", "two", "equal"])
+def test_parity_weight_orders(ctx, wmode):
+    """Distinct weights (bucket order), two weight classes (bitonic
+    fallback), equal weights (shuffled order)."""
+    sizes = [(300, 200), (97, 64), (512, 512), (40, 3)]
+    wl = custom_workload(sizes, seed=6, weight_mode=wmode)
+    _parity(ctx, wl, 0)
+    _parity(ctx, wl.copy(), 5, sort_by_weight=False)
+
+
+def test_parity_options(ctx):
+    wl = W.config2(n_cells=16)
+    _parity(ctx, wl.copy(), 1, moment_correction=False)
+    _parity(ctx, wl.copy(), 1, on_failure=1)
+    _parity(ctx, wl.copy(), 1, max_passes=3)
+    _parity(ctx, wl.copy(), 1, f_E=0.02)
+
+
+def test_parity_three_species_and_collision_order(ctx):
+    sizes = [(40, 30, 20), (7, 0, 5), (100, 101, 3)]
+    wl = custom_workload(sizes, seed=7, masses=(1.0, 4.0, 50.0), charges=(-1.0, 2.0, 3.0),
+                         collisions=((2, 0), (0, 0), (1, 2), (1, 1), (0, 1), (2, 2)))
+    _parity(ctx, wl, 4)
+
+
+def test_parity_relativistic_subset(ctx):
+    wl = W.config4(n_cells=8)
+    _parity(ctx, wl, 0)
+    wl2 = custom_workload([(50, 40), (13, 2), (300, 300)], seed=8, masses=(1.0, 1836.0),
+                          relativistic=True, c=1.0, dt=0.003)
+    _parity(ctx, wl2, 1)
+
+
+def test_diagnostics_show_roundoff_conservation(ctx):
+    wl = W.config2(n_cells=32)
+    _, sg, so = _parity(ctx, wl, 0, diagnostics=True)
+    assert sg["max_rel_dP"] < 1e-14 and sg["max_rel_dE"] < 1e-14
+
+
+def test_unsorted_entry_matches_oracle(ctx):
+    from paper_2407_19151_amd import native, runner
+    base = W.config2(n_cells=40)
+    wl = base.unsorted(seed=3)
+    v0 = wl.velocities().copy()
+    dw = runner.DeviceWorkload(wl)
+    runner.collide_unsorted(ctx, dw, 2)
+    vg = dw.velocities()
+    assert ctx.device_error() == 0
+    ref = wl.copy()
+    oracle.collide(ref.cells, ref.species, ref.n_cells, ref.mass, ref.charge, ref.collisions,
+                   ref.w, ref.vx, ref.vy, ref.vz, dt=ref.dt, coulomb_log=ref.coulomb_log,
+                   seed=ref.seed, step=2, method=ref.method)
+    check_parity(wl, vg, ref.velocities(), v0)
+
+
+def test_bin_is_bit_exact(ctx):
+    import torch
+    base = custom_workload([(5, 3), (0, 0), (300, 2), (4000, 1), (1, 1)], seed=9)
+    wl = base.unsorted(seed=4)
+    off, perm = ctx.bin(torch.from_numpy(wl.cells).cuda(), torch.from_numpy(wl.species).cuda(),
+                        wl.n_cells, wl.n_species)
+    ro, rp = oracle.bin_particles(wl.cells, wl.species, wl.n_cells, wl.n_species)
+    assert np.array_equal(off.cpu().numpy(), ro)
+    assert np.array_equal(perm.cpu().numpy().astype(np.int64), rp)
+
+
+def test_deterministic_reruns(ctx):
+    wl = W.config2(n_cells=24)
+    a, _, _ = _gpu_step(ctx, wl, 11)
+    b, _, _ = _gpu_step(ctx, wl, 11)
+    assert np.array_equal(a, b)
+
+
+def test_plan_graph_replay_equals_plain_steps(ctx):
+    """A plan with the default variants replays exactly the plain steps
+    (bitwise); an autotuned plan agrees to the parity bar (its per-cell sums
+    may run with another threads-per-cell, hence another rounding order)."""
+    from paper_2407_19151_amd import runner
+    wl = W.config3(n_cells=512)
+    dw1 = runner.DeviceWorkload(wl)
+    dw2 = runner.DeviceWorkload(wl)
+    dw3 = runner.DeviceWorkload(wl)
+    plan = runner.make_plan(ctx, dw1, autotune=False)
+    tuned = runner.make_plan(ctx, dw3, autotune=True)
+    try:
+        print(tuned.describe(), flush=True)
+        plan.run(first_step=5, n_steps=3)
+        tuned.run(first_step=5, n_steps=1)
+        for s in (5, 6, 7):
+            runner.collide_sorted(ctx, dw2, s, with_stats=False)
+            if s == 5:
+                v_after_5 = dw2.velocities()
+        assert np.array_equal(dw1.velocities(), dw2.velocities())
+        check_parity(wl, dw3.velocities(), v_after_5, wl.velocities())
+    finally:
+        plan.close()
+        tuned.close()
+
+
+VARIANTS = [(64, 128), (64, 256), (128, 256), (128, 512), (256, 512), (256, 1024),
+            (512, 1024), (512, 2048), (1024, 2048), (1024, 4096), (1024, 32768)]
+BUCKET_CAP = [128, 256, 512, 1024, 2048, 4096, 32768]
+
+
+@pytest.mark.parametrize("v", range(len(VARIANTS)))
+def test_every_kernel_variant_matches_oracle(ctx, v):
+    """Every compiled (threads per cell, capacity) variant on every bucket it
+    can serve, against the oracle."""
+    cap = VARIANTS[v][1]
+    sizes = [(60, 40), (111, 80), (300, 130), (600, 350), (1200, 700), (2300, 1600),
+             (3000, 3200)]
+    sizes = [s for s in sizes if sum(s) <= cap]
+    wl = custom_workload(sizes, seed=40 + v)
+    try:
+        for b, bc in enumerate(BUCKET_CAP):
+            if bc <= cap:
+                ctx.set_variant(b, v)
+        _parity(ctx, wl, 3)
+    finally:
+        for b in range(len(BUCKET_CAP)):
+            ctx.set_variant(b, -1)
+
+
+def test_invalid_offsets_flagged_not_faulting(ctx):
+    import torch
+    wl = W.config1(n_cells=4)
+    from paper_2407_19151_amd import runner
+    dw = runner.DeviceWorkload(wl)
+    bad = dw.offsets.clone()
+    bad[2] = bad[3] + 5  # not monotone
+    dw.offsets = bad
+    runner.collide_sorted(ctx, dw, 0)
+    assert ctx.device_error() == 1
+
+
+@pytest.mark.parametrize("method", [W.N97, W.TA77])
+def test_device_angle_sampler_matches_oracle_over_s_range(ctx, method):
+    """The map s -> (1 - cos theta, sin theta) on the device against the
+    oracle, over 16 decades of s and random uniforms (FP64)."""
+    import torch
+    rng = np.random.default_rng(17)
+    n = 20000
+    s = 10.0 ** rng.uniform(-12, 4, n)
+    a0 = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    a1 = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    oc, st, A = ctx.sample_angles(method, 0, torch.from_numpy(s).cuda(),
+                                  torch.from_numpy(a0.view(np.int32)).cuda(),
+                                  torch.from_numpy(a1.view(np.int32)).cuda())
+    oc, st, A = oc.cpu().numpy(), st.cpu().numpy(), A.cpu().numpy()
+    bad = []
+    for i in range(n):
+        u0 = (float(a0[i]) + 0.5) * 2.0 ** -32
+        u1 = (float(a1[i]) + 0.5) * 2.0 ** -32
+        ro, rs = oracle.sample_angle(method, float(s[i]), u0, u1)
+        if method == W.N97:
+            ra = oracle.n97_A(float(s[i]))
+            if not (abs(A[i] - ra) <= 1e-13 * abs(ra) or (ra == 0 and A[i] < 1e-300)):
+                bad.append(("A", i, s[i], A[i], ra))
+        if abs(oc[i] - ro) > 1e-12 * max(ro, 1e-300) + 1e-15 or abs(st[i] - rs) > 1e-12:
+            bad.append(("angle", i, s[i], u0, oc[i], ro, st[i], rs))
+    assert not bad, bad[:10]
