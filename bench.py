@@ -38,6 +38,10 @@ def parse():
     return ap.parse_args()
 
 
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def time_plan(plan, stream_sync, steps, warmup, first_step=1000):
     import torch
     plan.run(first_step, warmup)
@@ -83,6 +87,7 @@ def main():
     from paper_2407_19151_amd import workloads as W
 
     wl = W.config3(n_cells=args.cells)
+    log("workload: %d cells, %d particles" % (wl.n_cells, wl.n))
     pcs = wl.particle_collisions_per_step()
     ctx = native.Context(0)
     out = {}
@@ -92,7 +97,9 @@ def main():
         prec = native.MCC_FP32_KINEMATICS if mode == "fp32" else native.MCC_FP64
         plan = runner.make_plan(ctx, dw, params=runner.params_for(wl, precision=prec),
                                 autotune=not args.no_autotune)
+        log("%s plan built" % mode)
         ms, wall = time_plan(plan, torch.cuda.synchronize, args.steps, args.warmup)
+        log("%s timed: %.3f ms/step" % (mode, ms))
         desc = json.loads(plan.describe())
         plan.close()
         assert ctx.device_error() == 0
@@ -130,6 +137,7 @@ def main():
                              "roofline_frac": out["fp64"]["gbs"] / HBM_PEAK_GBS}
     res["plans"] = {m: o["plan"] for m, o in out.items()}
     if not args.no_cpu:
+        log("timing the CPU oracle on a sample")
         res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 

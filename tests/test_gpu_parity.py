@@ -48,7 +48,12 @@ def _parity(ctx, wl, step=0, tol=FP64_TOL, counts_exact=True, **over):
         oover["correction"] = oover.pop("moment_correction")
     so = oracle_step(ref, step, **oover)
     vr = ref.velocities()
-    info = check_parity(wl, vg, vr, v0, tol=tol)
+
+    def rerun(p):
+        oracle_step(p, step, **oover)
+        return p.velocities()
+
+    info = check_parity(wl, vg, vr, v0, tol=tol, rerun=rerun)
     print("  parity:", info, flush=True)
     assert sg["pairs"] == so["pairs"]
     assert sg["collisions"] == so["collisions"]
