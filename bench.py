@@ -3,15 +3,18 @@
 Workload: 65,536 cells with lognormal particle counts clipped to [16, 4096]
 (about 2.15e7 electrons and ions, mass ratio 100), N97, moment correction
 on, inputs resident in HBM.  The headline is the FP32-kinematics step
-(FP64 state, sums and correction) run as one HIP graph replay per step with
-autotuned threads-per-cell; the plain FP64 step on the same inputs is
-reported beside it.  Prints ONE JSON line.
+(FP64 state, sums and correction) run as one HIP graph replay per step; the
+plain FP64 step on the same inputs is reported beside it.  The kernel of
+each cell-size bucket is then timed alone (HIP events on the stream it runs
+on) and the slowest one is set against the HBM roofline.  Prints ONE JSON
+line.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--autotune]
+  python bench.py --copy-calibration MIB   (reference copy for the byte counters)
 """
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -21,8 +24,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-BYTES_PER_PARTICLE_STEP = 64  # cell 4 + species 4 + w 8 + v read 24 + v write 24
+# algorithmic HBM bytes per particle and step (sorted entry): w read 8,
+# v read 24, v write 24, and 8 for the cell and species ids a particle
+# carries (here implied by the offsets, whose per-group entries are < 0.1 %)
+BYTES_PER_PARTICLE_STEP = 64
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_c3_hbm_traffic.txt")
+BUCKET_CAP = [128, 256, 512, 1024, 2048, 4096, 32768]
 
 
 def parse():
@@ -33,8 +41,12 @@ def parse():
     ap.add_argument("--cells", type=int, default=65536)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time the candidate variants per bucket instead of the built-in table")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a device-to-device copy of MIB MiB three times (the "
+                         "reference reading for the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -42,12 +54,63 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def time_plan(plan, stream_sync, steps, warmup, first_step=1000):
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 3}), flush=True)
+
+
+def kernel_source_hash():
+    """sha256 over the HIP sources: byte counters taken from other sources
+    do not describe the kernels that run now."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2407_19151_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def read_traffic():
+    """Per-launch HBM bytes of each collide kernel from the committed
+    rocprofv3 counter summary, if it was taken from the current sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    table, src, ff, wf = {}, None, None, None
+    for line in open(TRAFFIC_FILE):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "source_sha256":
+            src = f[1]
+        elif f[0] == "fetch_factor":
+            ff = float(f[1])
+        elif f[0] == "write_factor":
+            wf = float(f[1])
+        elif f[0] == "kernel":
+            # kernel <mode> <tpc>x<cap> L<layout> fetch_kib <F> write_kib <W>
+            table[(f[1], f[2], f[3])] = (float(f[5]), float(f[7]))
+    if src != kernel_source_hash() or ff is None or wf is None:
+        return None
+    return {k: (fk * 1024 * ff + wk * 1024 * wf) for k, (fk, wk) in table.items()}
+
+
+def events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_plan(plan, steps, warmup, first_step=1000):
     import torch
     plan.run(first_step, warmup)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    e0, e1 = events()
     t0 = time.perf_counter()
     e0.record()
     plan.run(first_step + warmup, steps)
@@ -57,7 +120,31 @@ def time_plan(plan, stream_sync, steps, warmup, first_step=1000):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def cpu_baseline(wl, seconds):
+def time_buckets(plan, buckets, steps, first_step=5000):
+    """Average duration of each bucket's kernel, launched alone `steps` times
+    on the current stream (the one the plan launches on) between two events."""
+    import torch
+    out = {}
+    for b in buckets:
+        plan.run_bucket(b, first_step)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = events()
+        e0.record()
+        for k in range(steps):
+            plan.run_bucket(b, first_step + 1 + k)
+        e1.record()
+        torch.cuda.synchronize()
+        out[b] = e0.elapsed_time(e1) / steps
+    return out
+
+
+def bucket_particles(wl):
+    sizes = np.diff(wl.offsets[::wl.n_species])
+    b = np.searchsorted(np.asarray(BUCKET_CAP), sizes, side="left")
+    return {int(k): int(sizes[b == k].sum()) for k in np.unique(b)}
+
+
+def cpu_baseline(seconds):
     """The oracle, single-threaded, on a bounded sample of the same workload."""
     import oracle
     from paper_2407_19151_amd import workloads as W
@@ -73,14 +160,17 @@ def cpu_baseline(wl, seconds):
     dt = time.perf_counter() - t0
     return dict(value=pc * steps / dt, unit="particle-collisions/s", cores=1, kind="oracle",
                 sample="%d steps of the first 2048 cells of the same workload (%d particles, "
-                       "N97, FP64, correction on), single thread" % (steps, sub.n))
+                       "N97, FP64, correction on), one thread" % (steps, sub.n))
 
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(cells shard by range with no exchange; see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path here (cells shard "
+              "by range with no exchange; the design notes describe it)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2407_19151_amd import native, runner
@@ -89,6 +179,7 @@ def main():
     wl = W.config3(n_cells=args.cells)
     log("workload: %d cells, %d particles" % (wl.n_cells, wl.n))
     pcs = wl.particle_collisions_per_step()
+    per_bucket_n = bucket_particles(wl)
     ctx = native.Context(0)
     out = {}
     modes = ["fp32", "fp64"] if args.only is None else [args.only]
@@ -96,18 +187,32 @@ def main():
         dw = runner.DeviceWorkload(wl)
         prec = native.MCC_FP32_KINEMATICS if mode == "fp32" else native.MCC_FP64
         plan = runner.make_plan(ctx, dw, params=runner.params_for(wl, precision=prec),
-                                autotune=not args.no_autotune)
+                                autotune=args.autotune)
         log("%s plan built" % mode)
-        ms, wall = time_plan(plan, torch.cuda.synchronize, args.steps, args.warmup)
+        ms, wall = time_plan(plan, args.steps, args.warmup)
         log("%s timed: %.3f ms/step" % (mode, ms))
         desc = json.loads(plan.describe())
+        bms = time_buckets(plan, sorted(per_bucket_n), args.steps)
+        log("%s per-bucket kernel ms: %s" % (mode, {b: round(v, 4) for b, v in bms.items()}))
         plan.close()
         assert ctx.device_error() == 0
         gbs = BYTES_PER_PARTICLE_STEP * wl.n / (ms * 1e-3) / 1e9
-        out[mode] = dict(ms=ms, wall=wall, gbs=gbs, value=pcs / (ms * 1e-3), plan=desc)
+        out[mode] = dict(ms=ms, wall=wall, gbs=gbs, value=pcs / (ms * 1e-3), plan=desc,
+                         bucket_ms=bms)
         del dw
         torch.cuda.empty_cache()
-    head = out["fp32"] if "fp32" in out else out["fp64"]
+    head_mode = "fp32" if "fp32" in out else "fp64"
+    head = out[head_mode]
+    # dominant kernel: the bucket kernel with the longest launch
+    dom = max(head["bucket_ms"], key=lambda b: head["bucket_ms"][b])
+    dom_ms = head["bucket_ms"][dom]
+    bd = head["plan"]["buckets"][dom]
+    kname = "collide_kernel<%d, %d, %s, false, %d>" % (
+        bd["tpc"], bd["cap"], "float" if head_mode == "fp32" else "double", bd["layout"])
+    alg_bytes = BYTES_PER_PARTICLE_STEP * per_bucket_n[dom]
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = read_traffic()
+    tkey = (head_mode, "%dx%d" % (bd["tpc"], bd["cap"]), "L%d" % bd["layout"])
     res = {
         "metric": "particle-collisions/s per step + HBM roofline fraction, plain FP64 vs FP32+fix",
         "value": head["value"],
@@ -119,26 +224,33 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if "fp32" in out else "f64",
+        "dtype": "f32+f64" if head_mode == "fp32" else "f64",
         "data": "synthetic",
         "config": {"workload": "65536 cells, lognormal(ln 200, 1) counts clipped to [16, 4096], "
                                "electrons + ions (m_i/m_e = 100), N97, moment correction, "
                                "batched HIP-graph step",
                    "cells": wl.n_cells, "particles": wl.n,
                    "particle_collisions_per_step": pcs,
-                   "mode": "fp32 kinematics + fp64 correction" if "fp32" in out else "fp64"},
-        "roofline": {"bound": "hbm", "achieved": head["gbs"], "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": head["gbs"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "collide step (all size-bucket kernels of one graph replay)",
+                   "mode": ("fp32 kinematics + fp64 correction" if head_mode == "fp32"
+                            else "fp64"),
+                   "variants": "autotuned" if args.autotune else "built-in table"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (traffic.get(tkey) if traffic else None),
+                     "kernel": kname, "bucket_max_cell": BUCKET_CAP[dom],
+                     "bucket_particles": per_bucket_n[dom], "launch_ms": dom_ms,
+                     "algorithmic_bytes_per_launch": alg_bytes,
                      "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP},
+        "step_hbm_frac": head["gbs"] / HBM_PEAK_GBS,
+        "bucket_launch_ms": {str(BUCKET_CAP[b]): v for b, v in head["bucket_ms"].items()},
     }
     if "fp64" in out and "fp32" in out:
         res["plain_fp64"] = {"value": out["fp64"]["value"], "ms_per_step": out["fp64"]["ms"],
-                             "roofline_frac": out["fp64"]["gbs"] / HBM_PEAK_GBS}
+                             "step_hbm_frac": out["fp64"]["gbs"] / HBM_PEAK_GBS}
     res["plans"] = {m: o["plan"] for m, o in out.items()}
     if not args.no_cpu:
         log("timing the CPU oracle on a sample")
-        res["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 

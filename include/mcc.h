@@ -127,8 +127,9 @@ mcc_status mcc_device_error(mcc_ctx *ctx, int32_t *code);
  * non-plan entry points.  `variant` indexes the compiled (threads per cell,
  * capacity) table: 0 (64,128), 1 (64,256), 2 (128,256), 3 (128,512),
  * 4 (256,512), 5 (256,1024), 6 (512,1024), 7 (512,2048), 8 (1024,2048),
- * 9 (1024,4096, global scratch), 10 (1024,32768, global scratch); -1 restores
- * the default.  The variant's capacity must hold the bucket's largest cell,
+ * 9 (1024,4096), 10 (64,32768, one wave with global scratch), 11 (256,2048),
+ * 12 (512,4096), 13 (256,4096); in relativistic mode 9, 12 and 13 run as
+ * (64,4096) with global scratch.  -1 restores the default.  The variant's capacity must hold the bucket's largest cell,
  * else MCC_ERR_INVALID.  Results agree between variants to rounding (the
  * order of the per-cell sums depends on the threads per cell).
  */
@@ -222,7 +223,12 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n,
                            const mcc_params *p, mcc_stats *stats,
                            int32_t *cell_corr_pairs, int32_t autotune);
 mcc_status mcc_plan_run(mcc_plan *plan, uint64_t first_step, int32_t n_steps);
-/* Text description of the buckets and the chosen kernel variants. */
+/* The cells of one size bucket only (0..6, as for mcc_set_variant), one step
+ * `step`, launched directly rather than from the graph: for timing one kernel
+ * of the step.  Stats and per-cell counts accumulate without a reset. */
+mcc_status mcc_plan_run_bucket(mcc_plan *plan, int32_t bucket, uint64_t step);
+/* Text (JSON) description of the buckets: cell and particle counts, the
+ * chosen kernel variants and the autotuner's timings. */
 mcc_status mcc_plan_describe(mcc_plan *plan, char *buf, size_t len);
 void mcc_plan_destroy(mcc_plan *plan);
 

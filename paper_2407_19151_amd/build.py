@@ -25,15 +25,19 @@ def _hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
-    """Compile every HIP source and link the shared library (always rebuilds)."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, jobs: int = 8, out: str = LIB, defines=(),
+          build_dir: str = BUILD) -> str:
+    """Compile every HIP source and link the shared library (always rebuilds).
+    `defines` adds -D options (e.g. MCC_PHASE_TIMING for the per-phase clock
+    counters of a profiling build); `out` and `build_dir` place such a build
+    apart from the library the package loads."""
+    os.makedirs(build_dir, exist_ok=True)
     cc = _hipcc()
-    deps = [os.path.join(CSRC, f) for f in os.listdir(CSRC)]
+    dflags = ["-D" + d for d in defines]
 
     def one(src):
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        cmd = [cc, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        obj = os.path.join(build_dir, src.replace(".hip", ".o"))
+        cmd = [cc, *FLAGS, *dflags, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
@@ -43,14 +47,13 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(one, SOURCES))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s" % r.stderr[-8000:])
-    os.replace(tmp, LIB)
-    del deps
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

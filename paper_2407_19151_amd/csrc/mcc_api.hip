@@ -240,21 +240,38 @@ void set_big_args(mcc_ctx *ctx, CollideArgs &A, int mode, int v) {
   A.big_stride = big_stride_bytes(V.cap);
 }
 
-// enqueue the collide kernels of all buckets, reading their device work lists
+#ifdef MCC_PHASE_TIMING
+// profiling build: clock ticks per kernel phase, 16 counters per size bucket
+unsigned long long *g_phase = nullptr;
+#endif
+
+// enqueue the collide kernel of one bucket, reading its device work list
+mcc_status launch_bucket(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_t n_cells,
+                         const int32_t *lists, const uint32_t *counts, int b, int v,
+                         hipStream_t stream) {
+  const void *const *tab = kernel_table(mode);
+  if (!ensure_big(ctx, mode, v)) return MCC_ERR_OOM;
+  CollideArgs A = base;
+#ifdef MCC_PHASE_TIMING
+  A.phase = g_phase ? g_phase + 16 * b : nullptr;
+#endif
+  A.cell_list = lists + (int64_t)b * std::max(n_cells, 1);
+  A.cell_count = counts + b;
+  set_big_args(ctx, A, mode, v);
+  void *kargs[] = {&A};
+  HIP_TRY(hipLaunchKernel(tab[v], dim3(grid_of(ctx, mode, v)), dim3(variant_of(mode, v).tpc),
+                          kargs, 0, stream));
+  return MCC_OK;
+}
+
+// enqueue the collide kernels of all buckets, largest cells first
 mcc_status launch_buckets(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_t n_cells,
                           const int32_t *lists, const uint32_t *counts, const int *variant,
                           hipStream_t stream) {
-  const void *const *tab = kernel_table(mode);
   for (int b = NBUCKET - 1; b >= 0; --b) {
-    const int v = variant[b];
-    if (!ensure_big(ctx, mode, v)) return MCC_ERR_OOM;
-    CollideArgs A = base;
-    A.cell_list = lists + (int64_t)b * std::max(n_cells, 1);
-    A.cell_count = counts + b;
-    set_big_args(ctx, A, mode, v);
-    void *kargs[] = {&A};
-    HIP_TRY(hipLaunchKernel(tab[v], dim3(grid_of(ctx, mode, v)),
-                            dim3(variant_of(mode, v).tpc), kargs, 0, stream));
+    const mcc_status st =
+        launch_bucket(ctx, base, mode, n_cells, lists, counts, b, variant[b], stream);
+    if (st != MCC_OK) return st;
   }
   return MCC_OK;
 }
@@ -270,6 +287,19 @@ mcc_status finish(mcc_ctx *ctx) {
 }  // namespace
 
 extern "C" {
+
+#ifdef MCC_PHASE_TIMING
+// profiling build only (not part of the public header): copy out and
+// optionally clear the per-bucket phase counters
+int mcc_debug_phase_read(unsigned long long *out, int reset) {
+  if (!g_phase) return -1;
+  if (hipDeviceSynchronize() != hipSuccess) return -3;
+  const size_t bytes = sizeof(unsigned long long) * 16 * NBUCKET;
+  if (hipMemcpy(out, g_phase, bytes, hipMemcpyDeviceToHost) != hipSuccess) return -3;
+  if (reset && hipMemset(g_phase, 0, bytes) != hipSuccess) return -3;
+  return 0;
+}
+#endif
 
 void mcc_default_params(mcc_params *p) {
   if (!p) return;
@@ -325,6 +355,10 @@ mcc_status mcc_create(mcc_ctx **out, int device, void *hip_stream) {
     delete ctx;
     return from_hip(e);
   }
+#ifdef MCC_PHASE_TIMING
+  if (!g_phase && hipMalloc(&g_phase, sizeof(unsigned long long) * 16 * NBUCKET) == hipSuccess)
+    (void)hipMemset(g_phase, 0, sizeof(unsigned long long) * 16 * NBUCKET);
+#endif
   for (int m = 0; m < NMODE; ++m) {
     const void *const *tab = kernel_table(m);
     for (int v = 0; v < NVARIANT; ++v) {
@@ -637,6 +671,19 @@ mcc_status mcc_plan_run(mcc_plan *pl, uint64_t first_step, int32_t n_steps) {
   hipStream_t s = pl->ctx->stream;
   HIP_TRY(launch_set_u64(pl->step.as<uint64_t>(), first_step, s));
   for (int i = 0; i < n_steps; ++i) HIP_TRY(hipGraphLaunch(pl->exec, s));
+  return finish(pl->ctx);
+}
+
+mcc_status mcc_plan_run_bucket(mcc_plan *pl, int32_t bucket, uint64_t step) {
+  if (!pl || bucket < 0 || bucket >= NBUCKET) return MCC_ERR_INVALID;
+  HIP_TRY(hipSetDevice(pl->ctx->device));
+  CollideArgs A = pl->args;
+  A.step_dev = nullptr;
+  A.step = step;
+  const mcc_status st = launch_bucket(pl->ctx, A, pl->mode, pl->n_cells, pl->lists.as<int32_t>(),
+                                      pl->counts.as<uint32_t>(), bucket, pl->variant[bucket],
+                                      pl->ctx->stream);
+  if (st != MCC_OK) return st;
   return finish(pl->ctx);
 }
 

@@ -374,6 +374,24 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
   // bucket counters stay in LDS in every layout: global atomics complete in
   // L2, and later plain loads could hit stale L1 lines
   __shared__ __attribute__((aligned(16))) uint32_t lcnt[CAP + 2];
+#ifdef MCC_PHASE_TIMING
+  // profiling build: thread 0 charges the clock ticks between phase marks
+  __shared__ unsigned long long s_ph[16];
+  uint64_t ph_last = 0;
+  int ph_cur = 15;
+  if (threadIdx.x < 16) s_ph[threadIdx.x] = 0;
+#define MCC_PHASE(i)                                     \
+  do {                                                   \
+    if (threadIdx.x == 0) {                              \
+      const uint64_t now_ = clock64();                   \
+      if (ph_last) s_ph[ph_cur] += now_ - ph_last;       \
+      ph_last = now_;                                    \
+      ph_cur = (i);                                      \
+    }                                                    \
+  } while (0)
+#else
+#define MCC_PHASE(i) ((void)0)
+#endif
 
   CellMem M;
   double *wdst = nullptr;  // where the load phase copies the weights (LDS layout)
@@ -445,6 +463,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
   __syncthreads();
 
   for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
+    MCC_PHASE(0);  // header and staging
     const int cell = A.cell_list[li];
     // cell header: segment offsets, validated once
     if (t == 0) {
@@ -503,6 +522,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       if (intra ? (na < 2) : (na == 0 || nb == 0)) continue;
       const double ma = s_mass[a], mb = s_mass[b];
 
+      MCC_PHASE(1);  // snapshot and shuffles
       // pre-scatter snapshot (Alg. 1, first step)
       double bx[GL ? 1 : PPT], by[GL ? 1 : PPT], bz[GL ? 1 : PPT];
       for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
@@ -536,6 +556,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       //  intra, odd N : the triple (L0,L1),(L1,L2),(L2,L0) at s/2 in three
       //                 rounds; the regular pairs (L3,L4),... in round 0
       //  inter        : pair k = (big[k], small[k mod N_min]) in rounds of N_min
+      MCC_PHASE(2);  // scatter
       const uint32_t c3p = ctr3(step, k, PURPOSE_PAIR);
       const bool abig = na >= nb;
       const int Nmax = abig ? na : nb, Nmin = abig ? nb : na;
@@ -592,6 +613,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         s_st[3] += 1;
       }
 
+      MCC_PHASE(3);  // momentum restore and energy sums
       if (!A.corr) continue;
 
       auto part = [&](int e) {
@@ -669,6 +691,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         }
       }
 
+      MCC_PHASE(4);  // weight order
       // correction order per species (Alg. 1, optional sort), then the pair loop
       const int nsl = intra ? 1 : 2;
       uint16_t *O0 = M.list0, *O1 = M.list1;
@@ -687,6 +710,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       int used_total = 0;
       for (int pass = 0; pass < A.max_passes; ++pass) {
         if (resid0 == 0.0 && resid1 == 0.0) break;
+        MCC_PHASE(5);  // pair energies
         // K of every pair; pairs are disjoint, so each K is the value the
         // sequential loop of Alg. 1 sees
         const int np0 = (resid0 != 0.0) ? na / 2 : 0;
@@ -711,6 +735,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
           }
         }
         __syncthreads();
+        MCC_PHASE(6);  // sequential cut-off loop
         // the running violation, in the paper's order (one lane per species)
         {
           const int sl = (t == 0) ? 0 : ((NW > 1 && t == WAVE) ? 1 : -1);
@@ -747,6 +772,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
           }
         }
         __syncthreads();
+        MCC_PHASE(7);  // apply pair corrections
         // apply the pair corrections, Eqs. (19)-(22) / (A.3)-(A.5)
         const int nc0 = s_ncut[0], nc1 = s_ncut[1];
         for (int m = t; m < nc0 + nc1; m += TPC) {
@@ -790,6 +816,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         used_total += s_used[0] + s_used[1];
         __syncthreads();
       }
+      MCC_PHASE(8);  // failure handling and diagnostics
       const bool failed = resid0 != 0.0 || resid1 != 0.0;
       if (t == 0) {
         s_st[1] += used_total;
@@ -846,6 +873,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
 #undef SNAPZ
     }
 
+    MCC_PHASE(9);  // write-back
     __syncthreads();
     for (int e = t; e < n; e += TPC) {
       A.vx[cb + e] = M.vx[e];
@@ -869,6 +897,12 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
     }
     __syncthreads();
   }
+#ifdef MCC_PHASE_TIMING
+  MCC_PHASE(15);
+  if (threadIdx.x == 0 && A.phase)
+    for (int i = 0; i < 16; ++i) atomicAdd(&A.phase[i], s_ph[i]);
+#endif
+#undef MCC_PHASE
 }
 
 }  // namespace mcc

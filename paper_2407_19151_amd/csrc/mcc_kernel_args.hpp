@@ -36,6 +36,7 @@ struct CollideArgs {
   int32_t *err;                 // device error word
   char *big_scratch;            // large-cell variants: per-block global scratch
   uint64_t big_stride;          // bytes per block
+  unsigned long long *phase;    // profiling builds (MCC_PHASE_TIMING): clock ticks per phase
 };
 
 }  // namespace mcc

@@ -16,28 +16,28 @@ struct Variant {
   int layout;  // 0 LDS, 1 compact LDS, 2 global scratch
 };
 
-constexpr int NVARIANT = 11;
+constexpr int NVARIANT = 14;
 constexpr Variant kVariants[NVARIANT] = {
-    {64, 128, 0},   {64, 256, 0},   {128, 256, 0},   {128, 512, 0},
-    {256, 512, 0},  {256, 1024, 0}, {512, 1024, 0},  {512, 2048, 0},
-    {1024, 2048, 0}, {1024, 4096, 1}, {64, 32768, 2}};
+    {64, 128, 0},    {64, 256, 0},   {128, 256, 0},  {128, 512, 0},  {256, 512, 0},
+    {256, 1024, 0},  {512, 1024, 0}, {512, 2048, 0}, {1024, 2048, 0}, {1024, 4096, 1},
+    {64, 32768, 2},  {256, 2048, 0}, {512, 4096, 1}, {256, 4096, 1}};
 // the relativistic mode keeps a per-pair h(-mu) buffer, which the compact
-// layout has no room for: its 4096-cell variant uses global scratch
-constexpr Variant kRelVariant9 = {64, 4096, 2};
+// layout has no room for: its 4096-cell variants use global scratch
+constexpr Variant kRelVariant4096 = {64, 4096, 2};
 
 // cell-size buckets: bucket b holds cells with kBucketCap[b-1] < n <= kBucketCap[b]
 constexpr int NBUCKET = 7;
 constexpr int kBucketCap[NBUCKET] = {128, 256, 512, 1024, 2048, 4096, 32768};
-// default variant per bucket (the autotuner may pick another candidate)
-constexpr int kDefaultVariant[NBUCKET] = {0, 2, 4, 6, 8, 9, 10};
+// default variant per bucket (the fastest measured on lognormal cell-size
+// mixes; the autotuner may pick another candidate)
+constexpr int kDefaultVariant[NBUCKET] = {0, 1, 3, 5, 7, 12, 10};
 // candidates the autotuner times per bucket (-1 terminated)
 constexpr int kCandidates[NBUCKET][5] = {
-    {0, 1, 2, -1, -1}, {1, 2, 3, 4, -1}, {3, 4, 5, 6, -1}, {5, 6, 7, 8, -1},
-    {7, 8, -1, -1, -1}, {9, -1, -1, -1, -1}, {10, -1, -1, -1, -1}};
-
+    {0, 1, 2, -1, -1}, {1, 2, 3, 4, -1}, {3, 4, 5, 6, -1}, {5, 6, 7, 11, -1},
+    {7, 11, 8, -1, -1}, {12, 13, 9, -1, -1}, {10, -1, -1, -1, -1}};
 
 inline constexpr Variant variant_of(int mode, int v) {
-  return (mode == MODE_REL && v == 9) ? kRelVariant9 : kVariants[v];
+  return (mode == MODE_REL && kVariants[v].layout == 1) ? kRelVariant4096 : kVariants[v];
 }
 
 // global scratch bytes per workgroup of a global-layout variant:

@@ -31,7 +31,7 @@ EXPORTS = ["mcc_default_params", "mcc_status_string", "mcc_create", "mcc_set_str
            "mcc_set_variant",
            "mcc_destroy", "mcc_device_error", "mcc_collide_sorted", "mcc_collide",
            "mcc_bin", "mcc_plan_create", "mcc_plan_run", "mcc_plan_describe",
-           "mcc_plan_destroy", "mcc_sample_angles"]
+           "mcc_plan_destroy", "mcc_sample_angles", "mcc_plan_run_bucket"]
 
 
 class mcc_species(C.Structure):
@@ -73,6 +73,11 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError("libmcc_hip.so not found at %s: run __graft_entry__.build() "
                            "(or python -m paper_2407_19151_amd.build)" % path)
+    # torch ships its own HIP runtime with the same soname as the system one;
+    # loading torch first makes this library bind to that runtime, so the
+    # process holds one HIP runtime and torch's allocations and streams are
+    # valid here
+    import torch  # noqa: F401
     L = C.CDLL(path)
     P, i32, i64, u64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
     L.mcc_default_params.argtypes = [C.POINTER(mcc_params)]
@@ -103,6 +108,8 @@ def load(path: str = LIB_PATH):
     L.mcc_plan_create.restype = C.c_int
     L.mcc_plan_run.argtypes = [P, u64, i32]
     L.mcc_plan_run.restype = C.c_int
+    L.mcc_plan_run_bucket.argtypes = [P, i32, u64]
+    L.mcc_plan_run_bucket.restype = C.c_int
     L.mcc_plan_describe.argtypes = [P, C.c_char_p, C.c_size_t]
     L.mcc_plan_describe.restype = C.c_int
     L.mcc_sample_angles.argtypes = [P, i32, i32, i64, P, P, P, P, P, P]
@@ -348,6 +355,12 @@ class Plan:
     def run(self, first_step: int, n_steps: int = 1):
         self.ctx._stream()
         _check("mcc_plan_run", self.ctx.L.mcc_plan_run(self.h, int(first_step), int(n_steps)))
+
+    def run_bucket(self, bucket: int, step: int):
+        """Launch the kernel of one size bucket alone for one step."""
+        self.ctx._stream()
+        _check("mcc_plan_run_bucket",
+               self.ctx.L.mcc_plan_run_bucket(self.h, int(bucket), int(step)))
 
     def describe(self) -> str:
         buf = C.create_string_buffer(8192)
