@@ -37,7 +37,8 @@ hipError_t launch_bin(int64_t n, const int32_t *cells, const int32_t *species, i
                       hipStream_t s);
 hipError_t launch_sample_angles(int method, int precision, int64_t n, const double *s,
                                 const uint32_t *a0, const uint32_t *a1, double *oc, double *st,
-                                double *A, hipStream_t st_);
+                                double *A, const double2 *tab, hipStream_t st_);
+hipError_t launch_n97_table(double2 *tab, hipStream_t s);
 hipError_t launch_gather(int64_t n, const int32_t *perm, const double *w, const double *vx,
                          const double *vy, const double *vz, double *gw, double *gx, double *gy,
                          double *gz, hipStream_t s);
@@ -96,6 +97,7 @@ struct mcc_ctx {
   bool validate = false;
   int32_t *err = nullptr;  // device error word
   DevBuf lists, counts, big4k, big32k;
+  DevBuf n97;  // N97 A(s) table (built once)
   // unsorted entry
   DevBuf ucnt, tiles, off, cursor, perm, biglist, bigcount, canon, gw, gx, gy, gz;
   int grid[NMODE][NVARIANT] = {};
@@ -169,7 +171,7 @@ void fill_args(CollideArgs &A, int64_t n, int32_t n_cells, int32_t S, const int6
                const double *w, double *vx, double *vy, double *vz, const double *cell_volume,
                double dVs, const mcc_species *sp, int32_t n_coll, const mcc_collision *coll,
                double dt, double lnL, uint64_t seed, uint64_t step, const mcc_params *p,
-               mcc_stats *stats, int32_t *cell_corr, int32_t *err) {
+               mcc_stats *stats, int32_t *cell_corr, int32_t *err, const double2 *n97) {
   std::memset(&A, 0, sizeof(A));
   A.offsets = offsets;
   A.w = w;
@@ -211,6 +213,7 @@ void fill_args(CollideArgs &A, int64_t n, int32_t n_cells, int32_t S, const int6
   A.stats = stats;
   A.cell_corr = cell_corr;
   A.err = err;
+  A.n97 = n97;
 }
 
 bool ensure_lists(mcc_ctx *ctx, DevBuf &lists, DevBuf &counts, int32_t n_cells) {
@@ -351,6 +354,10 @@ mcc_status mcc_create(mcc_ctx **out, int device, void *hip_stream) {
   ctx->validate = val && val[0] == '1';
   e = hipMalloc(&ctx->err, sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(ctx->err, 0, sizeof(int32_t));
+  if (e == hipSuccess)
+    e = ctx->n97.ensure(sizeof(double2) * N97_TABLE_SIZE) ? hipSuccess : hipErrorOutOfMemory;
+  if (e == hipSuccess) e = launch_n97_table(ctx->n97.as<double2>(), nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     delete ctx;
     return from_hip(e);
@@ -384,7 +391,7 @@ void mcc_destroy(mcc_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->big4k, &ctx->big32k, &ctx->ucnt, &ctx->tiles,
                     &ctx->off, &ctx->cursor, &ctx->perm, &ctx->biglist, &ctx->bigcount,
-                    &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz})
+                    &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97})
     b->release();
   if (ctx->err) (void)hipFree(ctx->err);
   delete ctx;
@@ -410,7 +417,8 @@ mcc_status mcc_sample_angles(mcc_ctx *ctx, int32_t method, int32_t precision, in
     return MCC_ERR_INVALID;
   if (n > 0 && (!s || !a0 || !a1 || !oc || !st)) return MCC_ERR_INVALID;
   HIP_TRY(hipSetDevice(ctx->device));
-  HIP_TRY(launch_sample_angles(method, precision, n, s, a0, a1, oc, st, A, ctx->stream));
+  HIP_TRY(launch_sample_angles(method, precision, n, s, a0, a1, oc, st, A,
+                               ctx->n97.as<double2>(), ctx->stream));
   return finish(ctx);
 }
 
@@ -439,7 +447,7 @@ mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t 
   CollideArgs A;
   fill_args(A, n, n_cells, n_species, offsets, weights, vx, vy, vz, cell_volume,
             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, seed, step, p, stats,
-            cell_corr_pairs, ctx->err);
+            cell_corr_pairs, ctx->err, ctx->n97.as<double2>());
   hipStream_t s = ctx->stream;
   HIP_TRY(launch_fill_u32(ctx->counts.as<uint32_t>(), 0u, NBUCKET, s));
   if (stats) HIP_TRY(launch_zero_stats(stats, s));
@@ -561,7 +569,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
   }
   fill_args(pl->args, n, n_cells, n_species, offsets, weights, vx, vy, vz, cell_volume,
             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, seed, 0, p, stats,
-            cell_corr_pairs, ctx->err);
+            cell_corr_pairs, ctx->err, ctx->n97.as<double2>());
   pl->args.step_dev = pl->step.as<uint64_t>();
   hipStream_t s = ctx->stream;
   // device work lists, built once (offsets are fixed for the plan)

@@ -273,15 +273,27 @@ namespace mcc {
 // the angle sampler of the collision step, evaluated alone
 template <typename T>
 __global__ void k_sample_angles(int method, int64_t n, const double *s, const uint32_t *a0,
-                                const uint32_t *a1, double *oc, double *st, double *A) {
+                                const uint32_t *a1, double *oc, double *st, double *A,
+                                const double2 *tab) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     T o, t;
-    sample_angle<T>(method, (T)s[i], a0[i], a1[i], o, t);
+    sample_angle<T>(method, (T)s[i], a0[i], a1[i], o, t, tab);
     oc[i] = (double)o;
     st[i] = (double)t;
-    if (A) A[i] = method == 1 ? (double)n97_A<T>((T)s[i]) : 0.0;
+    if (A) A[i] = method == 1 ? (double)n97_A_fast<T>((T)s[i], tab) : 0.0;
   }
+}
+
+// the N97 table: A at the knots t_i = T0 + i h (s = e^t) from the bracketed
+// solver, and h dA/dt = -h s exp(-s) / L'(A) from differentiating L(A) = exp(-s)
+__global__ void k_n97_table(double2 *tab) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N97_TN) return;
+  const double s = exp(N97_T0 + i * N97_H);
+  const double A = n97_A<double>(s);
+  const double dAdt = -s * exp(-s) / langevin_deriv<double>(A);
+  tab[i] = make_double2(A, N97_H * dAdt);
 }
 }  // namespace mcc
 
@@ -378,16 +390,21 @@ hipError_t launch_bin(int64_t n, const int32_t *cells, const int32_t *species, i
   return hipGetLastError();
 }
 
+hipError_t launch_n97_table(double2 *tab, hipStream_t s) {
+  hipLaunchKernelGGL(k_n97_table, dim3((N97_TN + 63) / 64), dim3(64), 0, s, tab);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample_angles(int method, int precision, int64_t n, const double *s,
                                 const uint32_t *a0, const uint32_t *a1, double *oc, double *st,
-                                double *A, hipStream_t st_) {
+                                double *A, const double2 *tab, hipStream_t st_) {
   if (n <= 0) return hipSuccess;
   if (precision == 1)
     hipLaunchKernelGGL(k_sample_angles<float>, dim3(grid_for(n, 256)), dim3(256), 0, st_, method,
-                       n, s, a0, a1, oc, st, A);
+                       n, s, a0, a1, oc, st, A, tab);
   else
     hipLaunchKernelGGL(k_sample_angles<double>, dim3(grid_for(n, 256)), dim3(256), 0, st_,
-                       method, n, s, a0, a1, oc, st, A);
+                       method, n, s, a0, a1, oc, st, A, tab);
   return hipGetLastError();
 }
 

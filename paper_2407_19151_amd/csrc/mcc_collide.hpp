@@ -30,6 +30,7 @@ struct CellMem {
   double *vx, *vy, *vz;
   const double *w;        // LDS copy, or the read-only input (COMPACT)
   uint16_t *list0, *list1, *ord0, *ord1, *mem;
+  uint16_t *word;         // descending-weight order per species (not kept in the compact layout)
   uint32_t *key;          // shuffle keys (CAP)
   uint32_t *cnt;          // CAP+1 bucket counters, always LDS (atomics)
   double *kbuf;           // per-pair K / U of the energy loop (+ h(-mu) for REL)
@@ -44,7 +45,8 @@ template <typename KR>
 __device__ __forceinline__ void scatter_pair_nr(const CellMem &M, int I, int J, uint32_t kp,
                                                 double coef_f_nmin_dV, const CollConst &C,
                                                 int method, uint32_t cell, uint32_t step_lo,
-                                                uint32_t c3, uint32_t k0, uint32_t k1) {
+                                                uint32_t c3, uint32_t k0, uint32_t k1,
+                                                const double2 *n97tab) {
   using K = KMath<KR>;
   const double vix = M.vx[I], viy = M.vy[I], viz = M.vz[I];
   const double vjx = M.vx[J], vjy = M.vy[J], vjz = M.vz[J];
@@ -58,7 +60,7 @@ __device__ __forceinline__ void scatter_pair_nr(const CellMem &M, int I, int J, 
   if (!(s > KR(0))) return;
   const U4 r = philox(kp, cell, step_lo, c3, k0, k1);
   KR oc, st;
-  sample_angle<KR>(method, s, r.x, r.y, oc, st);
+  sample_angle<KR>(method, s, r.x, r.y, oc, st, n97tab);
   KR sp, cp;
   K::sincos2pi(K::u(r.z), sp, cp);
   KR dx, dy, dz;
@@ -92,7 +94,7 @@ __device__ __forceinline__ void scatter_pair_rel(const CellMem &M, int I, int J,
                                                  double coef_f_nmin_dV, double ma, double mb,
                                                  double c, int method, uint32_t cell,
                                                  uint32_t step_lo, uint32_t c3, uint32_t k0,
-                                                 uint32_t k1) {
+                                                 uint32_t k1, const double2 *n97tab) {
   const double c2 = c * c;
   const double uix = M.vx[I], uiy = M.vy[I], uiz = M.vz[I];
   const double ujx = M.vx[J], ujy = M.vy[J], ujz = M.vz[J];
@@ -128,7 +130,7 @@ __device__ __forceinline__ void scatter_pair_rel(const CellMem &M, int I, int J,
   const double psx = Qx / ecm + crx * kb, psy = Qy / ecm + cry * kb, psz = Qz / ecm + crz * kb;
   const U4 r = philox(kp, cell, step_lo, c3, k0, k1);
   double oc, st;
-  sample_angle<double>(method, s, r.x, r.y, oc, st);
+  sample_angle<double>(method, s, r.x, r.y, oc, st, n97tab);
   double sp, cp;
   KMath<double>::sincos2pi(unif64(r.z), sp, cp);
   double Dx, Dy, Dz;
@@ -286,28 +288,26 @@ __device__ __forceinline__ void shuffle_species(const CellMem &M, int ns, int of
   __syncthreads();
 }
 
-// Correction order of one species (Alg. 1, optional step): the shuffled list
-// L stably sorted by descending weight.  O receives cell-local indices.
+// Descending-weight order of ns particles, stable in list position (Alg. 1,
+// optional step): the particles are L[0..ns) (cell-local indices), or, with
+// L == nullptr, off, off+1, ..., off+ns-1.  O receives cell-local indices.
+// lo < hi are the bit patterns of the smallest and largest weight.
 template <int TPC, int PPT, bool G>
-__device__ __forceinline__ void weight_order(const CellMem &M, int ns, const uint16_t *L,
-                                             uint16_t *O, uint64_t lo, uint64_t hi,
-                                             uint32_t *wsum, uint32_t *maxocc) {
+__device__ __forceinline__ void weight_sort(const CellMem &M, int ns, const uint16_t *L, int off,
+                                            uint16_t *O, uint64_t lo, uint64_t hi,
+                                            uint32_t *wsum, uint32_t *maxocc) {
   const int t = threadIdx.x;
-  if (lo == hi) {  // all weights equal: the shuffled order itself
-    for (int q = t; q < ns; q += TPC) O[q] = L[q];
-    __syncthreads();
-    return;
-  }
   const double scale = (double)ns / ((double)(hi - lo) + 1.0);
   const double *w = M.w;
+  auto item = [&](int q) -> int { return L ? (int)L[q] : off + q; };
   auto before = [&](int o, int q) -> bool {
-    const double wo = w[L[o]], wq = w[L[q]];
+    const double wo = w[item(o)], wq = w[item(q)];
     return wo > wq || (wo == wq && o < q);
   };
   const uint32_t occ = bucket_rank_sort<TPC, PPT, G>(
       ns, M.cnt, M.mem, O, wsum, maxocc,
       [&](int q) -> uint32_t {
-        const uint64_t b = (uint64_t)__double_as_longlong(w[L[q]]);
+        const uint64_t b = (uint64_t)__double_as_longlong(w[item(q)]);
         const uint32_t k = (uint32_t)((double)(hi - b) * scale);
         return k < (uint32_t)ns ? k : (uint32_t)(ns - 1);
       },
@@ -323,9 +323,12 @@ __device__ __forceinline__ void weight_order(const CellMem &M, int ns, const uin
     for (int q = t; q < ns; q += TPC) O[q] = M.mem[q];
     __syncthreads();
   }
-  for (int q = t; q < ns; q += TPC) O[q] = L[O[q]];
+  for (int q = t; q < ns; q += TPC) O[q] = (uint16_t)item(O[q]);
   __syncthreads();
 }
+
+// weight classes of a species, decided once per cell
+enum : int { WORDER_EQUAL = 0, WORDER_DISTINCT = 1, WORDER_TIES = 2 };
 
 // Owner loop: particle e = threadIdx.x + j*TPC, j < PPT, unrolled when the
 // per-thread count is small.
@@ -359,11 +362,14 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
   static_assert(!(REL && LAY == LAYOUT_COMPACT), "REL needs the full pair buffer");
   static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
   __shared__ double red[2 * 6 * NW];
+  uint64_t *redu = reinterpret_cast<uint64_t *>(red);
   __shared__ uint32_t wsum[NW];
   __shared__ uint32_t maxocc;
   __shared__ int s_so[MCC_MAX_SPECIES + 1];
   __shared__ int s_bad;
   __shared__ unsigned long long s_wlo[MCC_MAX_SPECIES], s_whi[MCC_MAX_SPECIES];
+  __shared__ double s_sw[MCC_MAX_SPECIES], s_sw2[MCC_MAX_SPECIES];  // sum w, sum w^2
+  __shared__ int s_wflag[MCC_MAX_SPECIES];
   __shared__ unsigned long long s_st[4];  // pairs, correction pairs, failures, collisions
   __shared__ double s_sd[2];              // diagnostics maxima
   __shared__ int s_ncut[2];
@@ -401,7 +407,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
   if constexpr (LAY == LAYOUT_LDS) {
     __shared__ double lv[4 * CAP];
     __shared__ uint64_t lscr[CAP + 1];
-    __shared__ uint16_t lidx[5 * CAP];
+    __shared__ uint16_t lidx[6 * CAP];
     M.vx = lv;
     M.vy = lv + CAP;
     M.vz = lv + 2 * CAP;
@@ -414,6 +420,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
     M.ord0 = lidx + 2 * CAP;
     M.ord1 = lidx + 3 * CAP;
     M.mem = lidx + 4 * CAP;
+    M.word = lidx + 5 * CAP;
   } else if constexpr (LAY == LAYOUT_COMPACT) {
     __shared__ double lv[3 * CAP];
     __shared__ __attribute__((aligned(16))) uint16_t lidx[5 * CAP];
@@ -429,6 +436,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
     // energies live in the bucket counters (dead after the weight order)
     M.key = reinterpret_cast<uint32_t *>(lidx + 2 * CAP);
     M.kbuf = reinterpret_cast<double *>(lcnt);
+    M.word = M.mem;  // unused: no room here, species with unequal weights sort per collision
   } else {
     char *base = A.big_scratch + (uint64_t)blockIdx.x * A.big_stride;
     double *dv = reinterpret_cast<double *>(base);
@@ -449,6 +457,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
     M.ord0 = ix + 2 * CAP;
     M.ord1 = ix + 3 * CAP;
     M.mem = ix + 4 * CAP;
+    M.word = ix + 5 * CAP;
   }
 
   const int t = threadIdx.x;
@@ -483,17 +492,13 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       for (int q = 0; q < 4; ++q) s_st[q] = 0ull;
       s_sd[0] = s_sd[1] = 0.0;
     }
-    if (t < MCC_MAX_SPECIES) {
-      s_wlo[t] = ~0ull;
-      s_whi[t] = 0ull;
-    }
     __syncthreads();
     if (s_bad) {
       __syncthreads();
       continue;  // uniform over the workgroup
     }
     const int64_t cb = A.offsets[(int64_t)cell * S];
-    const int n = s_so[S];
+    const int n = uni(s_so[S]);
     const double dV = A.cell_volume ? A.cell_volume[cell] : A.dV;
     if constexpr (LAY == LAYOUT_COMPACT) M.w = A.w + cb;
 
@@ -501,26 +506,60 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       M.vx[e] = A.vx[cb + e];
       M.vy[e] = A.vy[cb + e];
       M.vz[e] = A.vz[cb + e];
-      const double we = A.w[cb + e];
-      if constexpr (LAY != LAYOUT_COMPACT) wdst[e] = we;
-      if (A.corr && A.sortw) {  // weight range per species (descending-weight order)
-        int s = 0;
-        while (s + 1 < S && e >= s_so[s + 1]) ++s;
-        const unsigned long long bits = (unsigned long long)__double_as_longlong(we);
-        atomicMin(&s_wlo[s], bits);
-        atomicMax(&s_whi[s], bits);
-      }
+      if constexpr (LAY != LAYOUT_COMPACT) wdst[e] = A.w[cb + e];
     }
     __syncthreads();
+    if (A.corr) {
+      // per species, once per cell: sum w and sum w^2 (the denominator of
+      // Eq. (17) and the mean weights of Eq. (24)), the weight range, and
+      // for unequal weights the descending-weight order, which is the
+      // correction order of every collision when no two weights are equal
+      for (int sp = 0; sp < S; ++sp) {
+        const int o = s_so[sp], ns = s_so[sp + 1] - o;
+        double acc[2] = {0.0, 0.0};
+        uint64_t lo[1] = {~0ull}, hi[1] = {0ull};
+        for (int e = o + t; e < o + ns; e += TPC) {
+          const double we = M.w[e];
+          acc[0] += we;
+          acc[1] += we * we;
+          const uint64_t bits = (uint64_t)__double_as_longlong(we);
+          lo[0] = bits < lo[0] ? bits : lo[0];
+          hi[0] = bits > hi[0] ? bits : hi[0];
+        }
+        double tot[2];
+        block_sum<TPC, 2>(acc, red, tot);
+        block_minmax_u64<TPC, 1>(lo, hi, redu);
+        int flag = WORDER_EQUAL;
+        if (A.sortw && ns >= 2 && lo[0] != hi[0]) {
+          flag = WORDER_TIES;
+          if constexpr (LAY != LAYOUT_COMPACT) {
+            weight_sort<TPC, PPT, GL>(M, ns, nullptr, o, M.word + o, lo[0], hi[0], wsum,
+                                      &maxocc);
+            int tie = 0;
+            for (int q = t; q + 1 < ns; q += TPC)
+              if (M.w[M.word[o + q]] == M.w[M.word[o + q + 1]]) tie = 1;
+            flag = __syncthreads_or(tie) ? WORDER_TIES : WORDER_DISTINCT;
+          }
+        }
+        if (t == 0) {
+          s_sw[sp] = tot[0];
+          s_sw2[sp] = tot[1];
+          s_wlo[sp] = lo[0];
+          s_whi[sp] = hi[0];
+          s_wflag[sp] = flag;
+        }
+      }
+      __syncthreads();
+    }
 
     for (int k = 0; k < A.n_coll; ++k) {
       const CollConst &C = s_coll[k];
-      const int a = C.a, b = C.b;
+      const int a = uni(C.a), b = uni(C.b);
       const bool intra = a == b;
-      const int oa = s_so[a], na = s_so[a + 1] - oa;
-      const int ob = s_so[b], nb = s_so[b + 1] - ob;
+      const int oa = uni(s_so[a]), na = uni(s_so[a + 1]) - oa;
+      const int ob = uni(s_so[b]), nb = uni(s_so[b + 1]) - ob;
       if (intra ? (na < 2) : (na == 0 || nb == 0)) continue;
-      const double ma = s_mass[a], mb = s_mass[b];
+      const double ma = uni(s_mass[a]), mb = uni(s_mass[b]);
 
       MCC_PHASE(1);  // snapshot and shuffles
       // pre-scatter snapshot (Alg. 1, first step)
@@ -601,10 +640,10 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
           const double cf = C.coef * f * (nmin / dV);
           if constexpr (REL)
             scatter_pair_rel(M, I, J, kp, cf, ma, mb, A.c, A.method, (uint32_t)cell, step_lo,
-                             c3p, k0, k1);
+                             c3p, k0, k1, A.n97);
           else
             scatter_pair_nr<KR>(M, I, J, kp, cf, C, A.method, (uint32_t)cell, step_lo, c3p, k0,
-                                k1);
+                                k1, A.n97);
         }
         __syncthreads();
       }
@@ -623,20 +662,19 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
 
       // momentum restore, Eq. (17): B = sum m_p (v_ps - v_bs) / sum m_p w_p
       {
-        CSum<4> P;
-        P.zero();
+        double P[3] = {0.0, 0.0, 0.0};
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
-                    if (e < n && part(e)) {
+          if (e < n && part(e)) {
             const double mp = mass_of(e) * M.w[e];
-            P.add(0, mp * (M.vx[e] - SNAPX(j, e)));
-            P.add(1, mp * (M.vy[e] - SNAPY(j, e)));
-            P.add(2, mp * (M.vz[e] - SNAPZ(j, e)));
-            P.add(3, mp * M.w[e]);
+            P[0] += mp * (M.vx[e] - SNAPX(j, e));
+            P[1] += mp * (M.vy[e] - SNAPY(j, e));
+            P[2] += mp * (M.vz[e] - SNAPZ(j, e));
           }
         });
-        double tot[4];
-        block_csum<TPC, 4>(P, red, tot);
-        const double Bx = tot[0] / tot[3], By = tot[1] / tot[3], Bz = tot[2] / tot[3];
+        double tot[3];
+        block_sum<TPC, 3>(P, red, tot);
+        const double D = ma * s_sw2[a] + (intra ? 0.0 : mb * s_sw2[b]);
+        const double Bx = tot[0] / D, By = tot[1] / D, Bz = tot[2] / D;
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
                     if (e < n && part(e)) {
             const double we = M.w[e];
@@ -649,59 +687,67 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       // energy violation, Eq. (18) (difference form), and the sums of Eq. (24)
       double dEs0, dEs1;
       {
-        CSum<5> E;
-        E.zero();
+        // per particle: the energy change (difference form, summed with
+        // compensation: its total is a small difference of large terms and
+        // decides how many pairs the correction uses) and, for an
+        // inter-species collision, the kinetic energy of each species
+        double es = 0.0, ec = 0.0;
+        double Ev[2] = {0.0, 0.0};
         const double c2 = A.c * A.c;
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
-                    if (e < n && part(e)) {
+          if (e < n && part(e)) {
             const bool isa = e >= oa && e < oa + na;
             const double mp = (isa ? ma : mb) * M.w[e];
             const double vx = M.vx[e], vy = M.vy[e], vz = M.vz[e];
             const double ox = SNAPX(j, e), oy = SNAPY(j, e), oz = SNAPZ(j, e);
             const double dd = (vx - ox) * (vx + ox) + (vy - oy) * (vy + oy) + (vz - oz) * (vz + oz);
-            const double vv = vx * vx + vy * vy + vz * vz;
             double term, ke;
             if constexpr (REL) {
+              const double vv = vx * vx + vy * vy + vz * vz;
               const double gv = sqrt(1.0 + vv / c2);
               const double gb = sqrt(1.0 + (ox * ox + oy * oy + oz * oz) / c2);
               term = mp * dd / (gv + gb);
               ke = mp * vv / (gv + 1.0);
             } else {
               term = 0.5 * mp * dd;
-              ke = 0.5 * mp * vv;
+              ke = 0.5 * mp * (vx * vx + vy * vy + vz * vz);
             }
-            E.add(0, term);
-            if (isa) {
-              E.add(1, ke);
-              E.add(3, M.w[e]);
-            } else {
-              E.add(2, ke);
-              E.add(4, M.w[e]);
-            }
+            csum_add(es, ec, term);
+            if (isa)
+              Ev[0] += ke;
+            else
+              Ev[1] += ke;
           }
         });
-        double tot[5];
-        block_csum<TPC, 5>(E, red, tot);
-        dEs0 = tot[0];
         dEs1 = 0.0;
-        if (!intra && tot[0] != 0.0) {
-          const double ea = tot[3] / na * tot[1], eb = tot[4] / nb * tot[2];
-          dEs0 = ea / (ea + eb) * tot[0];
-          dEs1 = eb / (ea + eb) * tot[0];
+        if (intra) {
+          double tot[1];
+          block_sum_c1<TPC, 1>(es, ec, Ev, red, dEs0, tot);
+        } else {
+          double tot[2];
+          block_sum_c1<TPC, 2>(es, ec, Ev, red, dEs0, tot);
+          if (dEs0 != 0.0) {
+            const double dE = dEs0;
+            const double ea = s_sw[a] / na * tot[0], eb = s_sw[b] / nb * tot[1];
+            dEs0 = ea / (ea + eb) * dE;
+            dEs1 = eb / (ea + eb) * dE;
+          }
         }
       }
 
-      MCC_PHASE(4);  // weight order
       // correction order per species (Alg. 1, optional sort), then the pair loop
       const int nsl = intra ? 1 : 2;
-      uint16_t *O0 = M.list0, *O1 = M.list1;
+      const uint16_t *O0 = M.list0, *O1 = M.list1;
       if (A.sortw) {
-        weight_order<TPC, PPT, GL>(M, na, M.list0, M.ord0, s_wlo[a], s_whi[a], wsum, &maxocc);
-        O0 = M.ord0;
-        if (!intra) {
-          weight_order<TPC, PPT, GL>(M, nb, M.list1, M.ord1, s_wlo[b], s_whi[b], wsum, &maxocc);
-          O1 = M.ord1;
-        }
+        auto order = [&](int sp, int o, int ns, const uint16_t *L, uint16_t *ord) {
+          const int f = s_wflag[sp];
+          if (f == WORDER_EQUAL) return L;  // all weights equal: the shuffled order
+          if (LAY != LAYOUT_COMPACT && f == WORDER_DISTINCT) return (const uint16_t *)(M.word + o);
+          weight_sort<TPC, PPT, GL>(M, ns, L, 0, ord, s_wlo[sp], s_whi[sp], wsum, &maxocc);
+          return (const uint16_t *)ord;
+        };
+        O0 = order(a, oa, na, M.list0, M.ord0);
+        if (!intra) O1 = order(b, ob, nb, M.list1, M.ord1);
       }
       double *Kb = M.kbuf;
       const int base1 = na / 2;           // pair slots of the second species

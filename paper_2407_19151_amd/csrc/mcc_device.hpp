@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mcc_kernel_args.hpp"
+
 namespace mcc {
 
 constexpr int WAVE = 64;
@@ -45,6 +47,15 @@ enum : uint32_t { PURPOSE_PAIR = 0, PURPOSE_SHUFFLE0 = 1 };
 
 __device__ __forceinline__ uint32_t ctr3(uint64_t step, int coll, uint32_t purpose) {
   return (uint32_t)(((step >> 32) & 0xFFFFu) << 16) | ((uint32_t)(coll & 0xFF) << 8) | purpose;
+}
+
+// values the whole wave holds alike (read from LDS): kept in scalar registers
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double uni(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // uniform in (0,1), exact in FP64
@@ -125,6 +136,90 @@ __device__ __forceinline__ void block_csum(CSum<N> &v, double *red, double out[N
       c = c + red[(w * N + i) * 2 + 1] + e;
     }
     out[i] = s + c;
+  }
+  __syncthreads();
+}
+
+// Plain FP64 sum of N values over the block; every thread receives the same
+// totals (the xor butterfly adds the same two operands on both partners).
+// `red` is LDS scratch of at least N*(TPC/64) doubles.  Ends with a barrier.
+template <int TPC, int N>
+__device__ __forceinline__ void block_sum(double v[N], double *red, double out[N]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  constexpr int NW = TPC / WAVE;
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off);
+  }
+  if (NW == 1) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = v[i];
+    __syncthreads();
+    return;
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[wid * N + i] = v[i];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double acc = red[i];
+    for (int w = 1; w < NW; ++w) acc += red[w * N + i];
+    out[i] = acc;
+  }
+  __syncthreads();
+}
+
+// One compensated value (s, c) and N plain values summed over the block in
+// one pass; every thread receives the totals.  `red` holds at least
+// (N+2)*(TPC/64) doubles.  Ends with a barrier.
+template <int TPC, int N>
+__device__ __forceinline__ void block_sum_c1(double &s, double &c, double v[N], double *red,
+                                             double &out_c, double out[N]) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  constexpr int NW = TPC / WAVE;
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    const double s2 = __shfl_xor(s, off), c2 = __shfl_xor(c, off);
+    double t, e;
+    two_sum(s, s2, t, e);
+    s = t;
+    c = c + c2 + e;
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off);
+  }
+  if (NW == 1) {
+    out_c = s + c;
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = v[i];
+    __syncthreads();
+    return;
+  }
+  constexpr int M = N + 2;
+  if (lane == 0) {
+    red[wid * M] = s;
+    red[wid * M + 1] = c;
+#pragma unroll
+    for (int i = 0; i < N; ++i) red[wid * M + 2 + i] = v[i];
+  }
+  __syncthreads();
+  double ss = red[0], cc = red[1];
+  for (int w = 1; w < NW; ++w) {
+    double t, e;
+    two_sum(ss, red[w * M], t, e);
+    ss = t;
+    cc = cc + red[w * M + 1] + e;
+  }
+  out_c = ss + cc;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double acc = red[2 + i];
+    for (int w = 1; w < NW; ++w) acc += red[w * M + 2 + i];
+    out[i] = acc;
   }
   __syncthreads();
 }
@@ -431,10 +526,91 @@ __device__ T n97_A(T s) {
   return A;
 }
 
+// ---------------------------------------------------------------------------
+// Fast A(s) for the collision step.  Nanbu's equation L(A) = coth A - 1/A =
+// exp(-s) has closed-form solutions to rounding at both ends; in between A
+// is interpolated (cubic Hermite in t = ln s on a table of A and dA/dt
+// computed once per context by n97_A above) and, in FP64, polished by one
+// Newton step on the equation itself (the interpolant is good to ~1e-9, so
+// one step reaches rounding).
+// ---------------------------------------------------------------------------
+constexpr int N97_TN = N97_TABLE_SIZE;
+constexpr double N97_T0 = -3.25;
+constexpr double N97_T1 = 3.0;
+constexpr double N97_H = (N97_T1 - N97_T0) / (N97_TN - 1);
+// below: 1 - L(A) = 1/A to 1e-20 relative (A > 24); above: L(A) = A/3 to
+// 1e-17 relative (A < 7e-9)
+constexpr double N97_S_LO = 0.04;
+constexpr double N97_S_HI = 20.0;
+
+// coth A - 1/A = sum_n c_n A^(2n-1) with c_n = 2^(2n) B_(2n) / (2n)!
+// (Bernoulli numbers B), convergent for |A| < pi; for A < 1/2 twelve terms
+// are below FP64 rounding.  Also returns the derivative.
+__device__ __forceinline__ void langevin_series(double A, double &L, double &dL) {
+  constexpr double c[12] = {
+      1.0 / 3.0,       -1.0 / 45.0,      2.0 / 945.0,         -1.0 / 4725.0,
+      2.0 / 93555.0,   -1382.0 / 638512875.0, 4.0 / 18243225.0, -3617.0 / 162820783125.0,
+      87734.0 / 38979295480125.0, -349222.0 / 1531329465290625.0,
+      310732.0 / 13447856940643125.0, -472728182.0 / 201919571963756521875.0};
+  const double x2 = A * A;
+  double p = c[11], q = 23.0 * c[11];
+#pragma unroll
+  for (int k = 10; k >= 0; --k) {
+    p = fma(p, x2, c[k]);
+    q = fma(q, x2, (2.0 * k + 1.0) * c[k]);
+  }
+  L = A * p;
+  dL = q;
+}
+
+// one Newton step on Nanbu's equation from A (FP64): the 1 - L form against
+// -expm1(-s) for s <= ln 2 (there A > 1.6), else the L form against exp(-s)
+__device__ __forceinline__ double n97_newton(double s, double A) {
+  double L, M, dL;
+  if (A < 0.5) {
+    langevin_series(A, L, dL);
+    M = 1.0 - L;
+  } else {
+    const double em1 = expm1(2.0 * A);
+    const double r1 = 1.0 / em1, ra = 1.0 / A;
+    M = ra - 2.0 * r1;
+    L = 1.0 - M;
+    dL = ra * ra - 4.0 * (em1 + 1.0) * r1 * r1;  // 1/A^2 - 1/sinh^2 A
+  }
+  double g;
+  if (s <= 0.69314718055994531)
+    g = -expm1(-s) - M;  // = L(A) - exp(-s), formed without cancellation
+  else
+    g = L - exp(-s);
+  return A - g / dL;
+}
+
+template <typename T>
+__device__ __forceinline__ T n97_A_fast(T s, const double2 *tab) {
+  using M = KMath<T>;
+  if (!(s > T(0))) return T(__builtin_inf());
+  if (s > M::S_ISO) return T(0);
+  if (s >= T(N97_S_HI)) return T(3) * M::exp_(-s);
+  if (s <= T(N97_S_LO)) return T(1) / (-M::expm1_(-s));
+  const T x = (M::log_(s) - T(N97_T0)) * T(1.0 / N97_H);
+  int i = (int)x;
+  i = i < 0 ? 0 : (i > N97_TN - 2 ? N97_TN - 2 : i);
+  const T f = x - T(i);
+  const double2 k0 = tab[i], k1 = tab[i + 1];
+  const T f2 = f * f, f3 = f2 * f;
+  // Hermite basis; the table holds A and h dA/dt at the knots
+  const T A = (T(2) * f3 - T(3) * f2 + T(1)) * T(k0.x) + (f3 - T(2) * f2 + f) * T(k0.y) +
+              (T(3) * f2 - T(2) * f3) * T(k1.x) + (f3 - f2) * T(k1.y);
+  if constexpr (sizeof(T) == 8)
+    return n97_newton(s, A);
+  else
+    return A;
+}
+
 // Sampled polar angle: oc = 1 - cos(theta), st = sin(theta).
 template <typename T>
 __device__ __forceinline__ void sample_angle(int method, T s, uint32_t a0, uint32_t a1, T &oc,
-                                             T &st) {
+                                             T &st, const double2 *n97tab) {
   using M = KMath<T>;
   const T u0 = M::u(a0);
   if (method == 0) {  // TA77: tan(theta/2) ~ N(0, s/2)
@@ -450,7 +626,7 @@ __device__ __forceinline__ void sample_angle(int method, T s, uint32_t a0, uint3
       oc = T(2) * d2 * q;
     }
   } else {  // N97
-    const T A = n97_A<T>(s);
+    const T A = n97_A_fast<T>(s, n97tab);
     if (__builtin_isinf(A))
       oc = T(0);
     else if (A == T(0))

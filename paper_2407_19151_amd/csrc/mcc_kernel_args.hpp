@@ -2,11 +2,15 @@
 // collide kernels (passed by value, one kernel argument).
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "../../include/mcc.h"
 
 namespace mcc {
+
+// knots of the N97 A(s) table (uniform in ln s)
+constexpr int N97_TABLE_SIZE = 256;
 
 // Per-collision constants computed on the host in FP64.
 struct CollConst {
@@ -37,6 +41,7 @@ struct CollideArgs {
   char *big_scratch;            // large-cell variants: per-block global scratch
   uint64_t big_stride;          // bytes per block
   unsigned long long *phase;    // profiling builds (MCC_PHASE_TIMING): clock ticks per phase
+  const double2 *n97;           // N97 table: A and h dA/dt at the knots of t = ln s
 };
 
 }  // namespace mcc

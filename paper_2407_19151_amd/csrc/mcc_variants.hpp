@@ -42,9 +42,9 @@ inline constexpr Variant variant_of(int mode, int v) {
 
 // global scratch bytes per workgroup of a global-layout variant:
 // 8 CAP doubles (v, w, snapshot, pair buffer), 2 CAP u32 (keys, slots),
-// 5 CAP u16 (lists, orders, bucket members)
+// 6 CAP u16 (lists, orders, bucket members, weight order)
 constexpr unsigned long long big_stride_bytes(int cap) {
-  return ((unsigned long long)cap * (8 * 8 + 2 * 4 + 5 * 2) + 255ull) & ~255ull;
+  return ((unsigned long long)cap * (8 * 8 + 2 * 4 + 6 * 2) + 255ull) & ~255ull;
 }
 
 }  // namespace mcc
