@@ -26,18 +26,18 @@ def _hipcc() -> str:
 
 
 def build(verbose: bool = False, jobs: int = 8, out: str = LIB, defines=(),
-          build_dir: str = BUILD) -> str:
+          build_dir: str = BUILD, csrc: str = CSRC) -> str:
     """Compile every HIP source and link the shared library (always rebuilds).
     `defines` adds -D options (e.g. MCC_PHASE_TIMING for the per-phase clock
-    counters of a profiling build); `out` and `build_dir` place such a build
-    apart from the library the package loads."""
+    counters of a profiling build); `out`, `build_dir` and `csrc` place such
+    a build apart from the library the package loads."""
     os.makedirs(build_dir, exist_ok=True)
     cc = _hipcc()
     dflags = ["-D" + d for d in defines]
 
     def one(src):
         obj = os.path.join(build_dir, src.replace(".hip", ".o"))
-        cmd = [cc, *FLAGS, *dflags, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *FLAGS, *dflags, "-c", os.path.join(csrc, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)
