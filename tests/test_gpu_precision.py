@@ -1,0 +1,111 @@
+"""The FP32-kinematics form against the FP64 oracle.
+
+In this form the pair kinematics (relative velocity, s, the angle and the
+rotation) run in FP32 from FP64-stored velocities, the increments are added
+in FP64 and the moment correction runs in FP64.  So the scatter differs
+from the oracle's by FP32 rounding, while momentum and energy stay exact to
+FP64 rounding (the FP64 correction removes the FP32 error together with the
+weighting error).
+
+Per-step tolerance: FP32 unit roundoff is 2^-24 = 6e-8; the kinematics chain
+(|u|, s ~ |u|^-3, A(s), the inverse CDF, sin/cos, the rotation) has a few
+tens of roundings and amplifies the relative error of |u| by at most 3
+through s, so the increment of a pair is good to ~3e-6 of |u|, and |u|
+reaches a few times the cell's RMS speed for tail particles: 1e-4 of the
+cell scale bounds it with margin.  Particles above that may only be members
+of an energy-correction pair whose cut-off moved (the same structural
+allowance as the FP64 tests: equal and opposite momentum change, parallel to
+the pair's relative velocity)."""
+import numpy as np
+import pytest
+
+from paper_2407_19151_amd import workloads as W
+
+from gpu_helpers import check_parity, oracle_step
+
+pytestmark = pytest.mark.gpu
+
+FP32_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_19151_amd import native
+    c = native.Context()
+    yield c
+    c.close()
+
+
+def _temps(wl, v):
+    """Per-species temperature sum(m w |v|^2) / (3 sum w)."""
+    m = wl.mass[wl.species]
+    out = []
+    for sp in range(wl.n_species):
+        k = wl.species == sp
+        out.append((m[k] * wl.w[k] * (v[:, k] ** 2).sum(0)).sum() / (3.0 * wl.w[k].sum()))
+    return np.array(out)
+
+
+@pytest.mark.parametrize("method", [W.N97, W.TA77])
+def test_fp32_kinematics_step_parity_and_exact_conservation(ctx, method):
+    from paper_2407_19151_amd import native, runner
+    wl = W.config2(n_cells=64, method=method)
+    v0 = wl.velocities().copy()
+    dw = runner.DeviceWorkload(wl)
+    runner.collide_sorted(ctx, dw, 3, params=runner.params_for(
+        wl, precision=native.MCC_FP32_KINEMATICS, diagnostics=True))
+    vg = dw.velocities()
+    st = native.read_stats(dw.stats)
+    assert ctx.device_error() == 0
+    ref = wl.copy()
+    so = oracle_step(ref, 3)
+    info = check_parity(wl, vg, ref.velocities(), v0, tol=FP32_TOL, cond_tol=0.2)
+    print("fp32 parity:", info, "stats:", st, flush=True)
+    assert st["pairs"] == so["pairs"] and st["collisions"] == so["collisions"]
+    assert st["failed"] == so["failed"]
+    # the FP64 correction leaves only FP64 rounding
+    assert st["max_rel_dP"] < 1e-14 and st["max_rel_dE"] < 1e-14
+
+
+def test_fp32_relaxation_rate_matches_fp64_oracle(ctx):
+    """Electron-ion temperature relaxation over 60 steps (256 cells of
+    Poisson(256) electrons and ions): the FP64 GPU trajectory follows the
+    oracle to rounding, and the FP32-kinematics one relaxes at the same rate
+    (fit of ln(T_e - T_i) against the step) within 1e-3 relative."""
+    from paper_2407_19151_amd import native, runner
+    wl = W.config2(n_cells=256)
+    steps = 60
+    traj = {}
+    for name, prec in (("fp64", native.MCC_FP64), ("fp32", native.MCC_FP32_KINEMATICS)):
+        dw = runner.DeviceWorkload(wl)
+        tr = []
+        for s in range(steps):
+            runner.collide_sorted(ctx, dw, s, params=runner.params_for(wl, precision=prec),
+                                  with_stats=False)
+            tr.append(_temps(wl, dw.velocities()))
+        traj[name] = np.array(tr)
+    assert ctx.device_error() == 0
+    ref = wl.copy()
+    tr = []
+    for s in range(steps):
+        oracle_step(ref, s)
+        tr.append(_temps(wl, ref.velocities()))
+    traj["oracle"] = np.array(tr)
+
+    def rate(T):
+        return -np.polyfit(np.arange(steps), np.log(T[:, 0] - T[:, 1]), 1)[0]
+
+    r = {k: rate(v) for k, v in traj.items()}
+    d64 = np.abs(traj["fp64"] / traj["oracle"] - 1).max()
+    d32 = np.abs(traj["fp32"] / traj["oracle"] - 1).max()
+    err32 = abs(r["fp32"] / r["oracle"] - 1)
+    print("relaxation rate per step: oracle %.6e fp64 %.6e fp32 %.6e; fp32 rate error %.2e; "
+          "max |T/T_oracle - 1|: fp64 %.2e fp32 %.2e" % (r["oracle"], r["fp64"], r["fp32"],
+                                                         err32, d64, d32), flush=True)
+    assert d64 < 1e-9
+    assert abs(r["fp64"] / r["oracle"] - 1) < 1e-9
+    assert d32 < 1e-3
+    assert err32 < 1e-3
