@@ -194,6 +194,34 @@ mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells,
                        int32_t *cell_corr_pairs);
 
 /*
+ * Forward-mode derivative of one step (the differentiated form): the same
+ * step as mcc_collide_sorted (FP64, non-relativistic), carrying the tangent
+ * (tx, ty, tz) of the velocities, device double[n] in/out, and the tangent
+ * coulomb_log_tangent of ln(Lambda) (Eq. (12): s is proportional to it).  On
+ * return (tx, ty, tz) hold J (t, dlnL) where J is the Jacobian of the step
+ * with every random number and every discrete choice of the primal fixed:
+ * the pairing, the acceptances, the correction order, the cut pair of
+ * Eq. (23) and the failure decision.  The N97 parameter is differentiated as
+ * the root of Nanbu's equation (dA/ds = -exp(-s)/L'(A)).  update_primal = 0
+ * leaves (vx, vy, vz) unchanged (several tangents of one state); 1 also
+ * writes the primal step.  Diagnostics and per-cell counts are not
+ * produced; stats (nullable) counts as for mcc_collide_sorted.
+ * Errors: MCC_ERR_UNSUPPORTED for the relativistic or FP32 forms;
+ * MCC_ERR_INVALID for a nonzero lnL tangent with lnL <= 0.
+ */
+mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells,
+                                  int32_t n_species, const int64_t *offsets,
+                                  const double *weights, double *vx, double *vy,
+                                  double *vz, double *tx, double *ty, double *tz,
+                                  const double *cell_volume,
+                                  double cell_volume_scalar,
+                                  const mcc_species *species, int32_t n_coll,
+                                  const mcc_collision *coll, double dt,
+                                  double coulomb_log, double coulomb_log_tangent,
+                                  uint64_t seed, uint64_t step, const mcc_params *p,
+                                  int32_t update_primal, mcc_stats *stats);
+
+/*
  * Cell binning alone (the grouping used by mcc_collide):
  *  offsets_out  device int64[n_cells*n_species + 1]
  *  perm_out     device int32[n]: perm_out[j] = original index of the j-th

@@ -19,6 +19,7 @@
 const void *const *mcc_kernel_table_fp64();
 const void *const *mcc_kernel_table_fp32();
 const void *const *mcc_kernel_table_rel();
+const void *const *mcc_kernel_table_tan();
 
 namespace mcc {
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -84,6 +85,7 @@ const void *const *kernel_table(int mode) {
   switch (mode) {
     case MODE_FP64: return mcc_kernel_table_fp64();
     case MODE_FP32: return mcc_kernel_table_fp32();
+    case MODE_TAN: return mcc_kernel_table_tan();
     default: return mcc_kernel_table_rel();
   }
 }
@@ -231,7 +233,7 @@ int grid_of(mcc_ctx *ctx, int mode, int v) {
 bool ensure_big(mcc_ctx *ctx, int mode, int v) {
   const Variant V = variant_of(mode, v);
   if (V.layout != 2) return true;
-  const uint64_t stride = big_stride_bytes(V.cap);
+  const uint64_t stride = big_stride_bytes(V.cap, mode == MODE_TAN);
   if (V.cap > 4096) return ctx->big32k.ensure(stride * BIG32K_GRID);
   return ctx->big4k.ensure(stride * (uint64_t)ctx->n_cu);
 }
@@ -240,7 +242,7 @@ void set_big_args(mcc_ctx *ctx, CollideArgs &A, int mode, int v) {
   const Variant V = variant_of(mode, v);
   if (V.layout != 2) return;
   A.big_scratch = V.cap > 4096 ? ctx->big32k.as<char>() : ctx->big4k.as<char>();
-  A.big_stride = big_stride_bytes(V.cap);
+  A.big_stride = big_stride_bytes(V.cap, mode == MODE_TAN);
 }
 
 #ifdef MCC_PHASE_TIMING
@@ -455,6 +457,48 @@ mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t 
   HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, ctx->lists.as<int32_t>(),
                               ctx->counts.as<uint32_t>(), cell_corr_pairs, ctx->err, s));
   st = launch_buckets(ctx, A, mode_of(p), n_cells, ctx->lists.as<int32_t>(),
+                      ctx->counts.as<uint32_t>(), ctx->variant, s);
+  if (st != MCC_OK) return st;
+  return finish(ctx);
+}
+
+mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                                  const int64_t *offsets, const double *weights, double *vx,
+                                  double *vy, double *vz, double *tx, double *ty, double *tz,
+                                  const double *cell_volume, double cell_volume_scalar,
+                                  const mcc_species *species, int32_t n_coll,
+                                  const mcc_collision *coll, double dt, double coulomb_log,
+                                  double coulomb_log_tangent, uint64_t seed, uint64_t step,
+                                  const mcc_params *p, int32_t update_primal,
+                                  mcc_stats *stats) {
+  if (!ctx || !offsets) return MCC_ERR_INVALID;
+  mcc_status st = check_step(n, n_cells, n_species, weights, vx, vy, vz, cell_volume,
+                             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, p);
+  if (st != MCC_OK) return st;
+  if (n > 0 && (!tx || !ty || !tz)) return MCC_ERR_INVALID;
+  if (!std::isfinite(coulomb_log_tangent)) return MCC_ERR_INVALID;
+  if (coulomb_log_tangent != 0.0 && !(coulomb_log > 0.0)) return MCC_ERR_INVALID;
+  if (p->relativistic || p->precision != MCC_FP64) return MCC_ERR_UNSUPPORTED;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (!ensure_lists(ctx, ctx->lists, ctx->counts, n_cells)) return MCC_ERR_OOM;
+  CollideArgs A;
+  mcc_params q = *p;
+  q.diagnostics = 0;
+  fill_args(A, n, n_cells, n_species, offsets, weights, vx, vy, vz, cell_volume,
+            cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, seed, step, &q, stats,
+            nullptr, ctx->err, ctx->n97.as<double2>());
+  A.tx = tx;
+  A.ty = ty;
+  A.tz = tz;
+  A.dlnl = coulomb_log_tangent != 0.0 ? coulomb_log_tangent / coulomb_log : 0.0;
+  A.write_primal = update_primal ? 1 : 0;
+  hipStream_t s = ctx->stream;
+  HIP_TRY(launch_fill_u32(ctx->counts.as<uint32_t>(), 0u, NBUCKET, s));
+  if (stats) HIP_TRY(launch_zero_stats(stats, s));
+  if (n_cells == 0) return finish(ctx);
+  HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, ctx->lists.as<int32_t>(),
+                              ctx->counts.as<uint32_t>(), nullptr, ctx->err, s));
+  st = launch_buckets(ctx, A, MODE_TAN, n_cells, ctx->lists.as<int32_t>(),
                       ctx->counts.as<uint32_t>(), ctx->variant, s);
   if (st != MCC_OK) return st;
   return finish(ctx);

@@ -19,6 +19,7 @@
 
 #include "mcc_device.hpp"
 #include "mcc_kernel_args.hpp"
+#include "mcc_variants.hpp"
 
 namespace mcc {
 
@@ -36,6 +37,9 @@ struct CellMem {
   double *kbuf;           // per-pair K / U of the energy loop (+ h(-mu) for REL)
   uint32_t *slotbuf;      // GLOBAL: per-item bucket slots
   double *bx, *by, *bz;   // GLOBAL: pre-scatter snapshot
+  // tangent form: tangent of the velocities, its pre-scatter snapshot, and
+  // per-pair tangents of K (then of U)
+  double *tx, *ty, *tz, *btx, *bty, *btz, *kdot;
 };
 
 // ---------------------------------------------------------------------------
@@ -95,6 +99,115 @@ __device__ __attribute__((noinline)) void scatter_pair_nr_f64(
     uint32_t c3, uint32_t k0, uint32_t k1, const double2 *n97tab) {
   scatter_pair_nr<double>(vx, vy, vz, w, I, J, kp, coef_f_nmin_dV, fa, fb, method, cell, step_lo,
                           c3, k0, k1, n97tab);
+}
+
+// ---------------------------------------------------------------------------
+// Tangent (forward-mode) pair scatter, FP64: the primal update exactly as
+// scatter_pair_nr<double>, and the derivative of the pair's new velocities
+// along the tangent (t of the velocities, dlnl = d lnL / lnL) with the
+// random numbers and the acceptance fixed.  A(s) is differentiated as the
+// root of Nanbu's equation: dA/ds = -exp(-s) / L'(A).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double langevin_prime(double A) {
+  if (A < 0.5) {
+    double L, dL;
+    langevin_series(A, L, dL);
+    return dL;
+  }
+  // 1/sinh^2 A = 4 e^{-2A} / (1 - e^{-2A})^2, finite for every A
+  const double em = expm1(-2.0 * A), ra = 1.0 / A;
+  return ra * ra - 4.0 * (em + 1.0) / (em * em);
+}
+
+__device__ __attribute__((noinline)) void scatter_pair_nr_tan(
+    double *vx, double *vy, double *vz, double *tx, double *ty, double *tz, const double *w,
+    int I, int J, uint32_t kp, double coef_f_nmin_dV, double fa, double fb, int method,
+    uint32_t cell, uint32_t step_lo, uint32_t c3, uint32_t k0, uint32_t k1,
+    const double2 *n97tab, double dlnl) {
+  using K = KMath<double>;
+  const double vix = vx[I], viy = vy[I], viz = vz[I];
+  const double vjx = vx[J], vjy = vy[J], vjz = vz[J];
+  const double wi = w[I], wj = w[J];
+  const double ux = vix - vjx, uy = viy - vjy, uz = viz - vjz;
+  const double um2 = ux * ux + uy * uy + uz * uz;
+  if (um2 == 0.0) return;
+  const double um = K::sqrt_(um2);
+  const double wmax = wi > wj ? wi : wj;
+  const double s = (coef_f_nmin_dV * wmax) / (um2 * um);
+  if (!(s > 0.0)) return;
+  const U4 r = philox(kp, cell, step_lo, c3, k0, k1);
+  double oc, st;
+  sample_angle<double>(method, s, r.x, r.y, oc, st, n97tab);
+  double sp, cp;
+  K::sincos2pi(K::u(r.z), sp, cp);
+  double dx, dy, dz;
+  rotate_delta<double>(ux, uy, uz, st, oc, sp, cp, dx, dy, dz);
+  const double u3 = unif64(r.w);
+  bool ai = true, aj = true;
+  if (wi < wj)
+    aj = u3 <= wi / wj;
+  else if (wj < wi)
+    ai = u3 <= wj / wi;
+
+  // tangent of u, |u| and s (s ~ lnL / |u|^3)
+  const double tux = tx[I] - tx[J], tuy = ty[I] - ty[J], tuz = tz[I] - tz[J];
+  const double tum = (ux * tux + uy * tuy + uz * tuz) / um;
+  const double ts = s * (dlnl - 3.0 * tum / um);
+  // tangent of 1 - cos(theta) and sin(theta)
+  double toc = 0.0;
+  if (method == 0) {  // TA77: delta = sqrt(s/2) z scales as sqrt(s)
+    if (oc < 2.0) {
+      const double d2 = oc / (2.0 - oc);  // delta^2, from oc = 2 d2 / (1 + d2)
+      // d oc / d(delta^2) = 2 / (1 + d2)^2 and d(delta^2) = delta^2 ds / s
+      toc = 2.0 / ((1.0 + d2) * (1.0 + d2)) * d2 * ts / s;
+    }
+  } else {
+    const double A = n97_A_fast<double>(s, n97tab);
+    if (A > 0.0 && !__builtin_isinf(A) && oc > 0.0 && oc < 2.0) {
+      const double e = expm1(-2.0 * A);
+      const double den = 1.0 + K::u(r.x) * e;
+      const double dl_dA = -2.0 * K::u(r.x) * (e + 1.0) / den;  // d log1p(u0 e) / dA
+      const double doc_dA = -dl_dA / A - oc / A;
+      const double dA_ds = -exp(-s) / langevin_prime(A);
+      toc = doc_dA * dA_ds * ts;
+    }
+  }
+  // st^2 = oc (2 - oc) for either sign of st
+  const double tst = st != 0.0 ? (1.0 - oc) * toc / st : 0.0;
+  // tangent of the rotation
+  double tdx, tdy, tdz;
+  const double up2 = ux * ux + uy * uy;
+  const double up = K::sqrt_(up2);
+  if (up > 0.0) {
+    const double tup = (ux * tux + uy * tuy) / up;
+    const double ax = ux / up, ay = uy / up;
+    const double tax = (tux - ax * tup) / up, tay = (tuy - ay * tup) / up;
+    tdx = tax * uz * st * cp + ax * (tuz * st + uz * tst) * cp - tay * um * st * sp -
+          ay * (tum * st + um * tst) * sp - tux * oc - ux * toc;
+    tdy = tay * uz * st * cp + ay * (tuz * st + uz * tst) * cp + tax * um * st * sp +
+          ax * (tum * st + um * tst) * sp - tuy * oc - uy * toc;
+    tdz = -(tup * st + up * tst) * cp - tuz * oc - uz * toc;
+  } else {
+    tdx = (tum * st + um * tst) * cp;
+    tdy = (tum * st + um * tst) * sp;
+    tdz = -tuz * oc - uz * toc;
+  }
+  if (ai) {
+    vx[I] = vix + fa * dx;
+    vy[I] = viy + fa * dy;
+    vz[I] = viz + fa * dz;
+    tx[I] += fa * tdx;
+    ty[I] += fa * tdy;
+    tz[I] += fa * tdz;
+  }
+  if (aj) {
+    vx[J] = vjx - fb * dx;
+    vy[J] = vjy - fb * dy;
+    vz[J] = vjz - fb * dz;
+    tx[J] -= fb * tdx;
+    ty[J] -= fb * tdy;
+    tz[J] -= fb * tdz;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -364,7 +477,7 @@ __device__ __forceinline__ void for_owned(int n, F &&f) {
 // ---------------------------------------------------------------------------
 // The kernel
 // ---------------------------------------------------------------------------
-template <int TPC, int CAP, typename KR, bool REL, int LAY>
+template <int TPC, int CAP, typename KR, bool REL, int LAY, bool TAN = false>
 __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
   constexpr int PPT = CAP / TPC;
   constexpr int NW = TPC / WAVE;
@@ -373,6 +486,8 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
   static_assert(CAP % TPC == 0 && TPC % WAVE == 0, "bad variant");
   static_assert(!(REL && LAY == LAYOUT_COMPACT), "REL needs the full pair buffer");
   static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
+  static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT),
+                "the tangent form is FP64 non-relativistic");
   __shared__ double red[2 * 6 * NW];
   uint64_t *redu = reinterpret_cast<uint64_t *>(red);
   __shared__ uint32_t wsum[NW];
@@ -386,6 +501,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
   __shared__ double s_sd[2];              // diagnostics maxima
   __shared__ int s_ncut[2];
   __shared__ double s_res[2];
+  __shared__ double s_tres[2];  // tangent form: tangent of the residuals
   __shared__ int s_used[2];
   __shared__ double s_mass[MCC_MAX_SPECIES];
   __shared__ CollConst s_coll[MCC_MAX_COLLISIONS];
@@ -433,6 +549,16 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
     M.ord1 = lidx + 3 * CAP;
     M.mem = lidx + 4 * CAP;
     M.word = lidx + 5 * CAP;
+    if constexpr (TAN) {
+      __shared__ double lt[7 * CAP];
+      M.tx = lt;
+      M.ty = lt + CAP;
+      M.tz = lt + 2 * CAP;
+      M.btx = lt + 3 * CAP;
+      M.bty = lt + 4 * CAP;
+      M.btz = lt + 5 * CAP;
+      M.kdot = lt + 6 * CAP;
+    }
   } else if constexpr (LAY == LAYOUT_COMPACT) {
     __shared__ double lv[3 * CAP];
     __shared__ __attribute__((aligned(16))) uint16_t lidx[5 * CAP];
@@ -470,6 +596,16 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
     M.ord1 = ix + 3 * CAP;
     M.mem = ix + 4 * CAP;
     M.word = ix + 5 * CAP;
+    if constexpr (TAN) {
+      double *lt = reinterpret_cast<double *>(base + big_stride_bytes(CAP, false));
+      M.tx = lt;
+      M.ty = lt + CAP;
+      M.tz = lt + 2 * CAP;
+      M.btx = lt + 3 * CAP;
+      M.bty = lt + 4 * CAP;
+      M.btz = lt + 5 * CAP;
+      M.kdot = lt + 6 * CAP;
+    }
   }
 
   const int t = threadIdx.x;
@@ -519,6 +655,11 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       M.vy[e] = A.vy[cb + e];
       M.vz[e] = A.vz[cb + e];
       if constexpr (LAY != LAYOUT_COMPACT) wdst[e] = A.w[cb + e];
+      if constexpr (TAN) {
+        M.tx[e] = A.tx[cb + e];
+        M.ty[e] = A.ty[cb + e];
+        M.tz[e] = A.tz[cb + e];
+      }
     }
     __syncthreads();
     if (A.corr) {
@@ -577,7 +718,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       // pre-scatter snapshot (Alg. 1, first step)
       double bx[GL ? 1 : PPT], by[GL ? 1 : PPT], bz[GL ? 1 : PPT];
       for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
-                if (e < n) {
+        if (e < n) {
           if constexpr (BIG) {
             M.bx[e] = M.vx[e];
             M.by[e] = M.vy[e];
@@ -586,6 +727,11 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
             bx[j] = M.vx[e];
             by[j] = M.vy[e];
             bz[j] = M.vz[e];
+          }
+          if constexpr (TAN) {
+            M.btx[e] = M.tx[e];
+            M.bty[e] = M.ty[e];
+            M.btz[e] = M.tz[e];
           }
         }
       });
@@ -653,6 +799,9 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
           if constexpr (REL)
             scatter_pair_rel(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, ma, mb, A.c, A.method,
                              (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
+          else if constexpr (TAN)
+            scatter_pair_nr_tan(M.vx, M.vy, M.vz, M.tx, M.ty, M.tz, M.w, I, J, kp, cf, C.fa, C.fb,
+                                A.method, (uint32_t)cell, step_lo, c3p, k0, k1, A.n97, A.dlnl);
           else if constexpr (sizeof(KR) == 8)
             scatter_pair_nr_f64(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, C.fa, C.fb, A.method,
                                 (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
@@ -677,19 +826,38 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
 
       // momentum restore, Eq. (17): B = sum m_p (v_ps - v_bs) / sum m_p w_p
       {
-        double P[3] = {0.0, 0.0, 0.0};
+        constexpr int NP = TAN ? 6 : 3;  // the tangent of the sums rides along
+        double P[NP];
+#pragma unroll
+        for (int i = 0; i < NP; ++i) P[i] = 0.0;
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
           if (e < n && part(e)) {
             const double mp = mass_of(e) * M.w[e];
             P[0] += mp * (M.vx[e] - SNAPX(j, e));
             P[1] += mp * (M.vy[e] - SNAPY(j, e));
             P[2] += mp * (M.vz[e] - SNAPZ(j, e));
+            if constexpr (TAN) {
+              P[3 % NP] += mp * (M.tx[e] - M.btx[e]);
+              P[4 % NP] += mp * (M.ty[e] - M.bty[e]);
+              P[5 % NP] += mp * (M.tz[e] - M.btz[e]);
+            }
           }
         });
-        double tot[3];
-        block_sum<TPC, 3>(P, red, tot);
+        double tot[NP];
+        block_sum<TPC, NP>(P, red, tot);
         const double D = ma * s_sw2[a] + (intra ? 0.0 : mb * s_sw2[b]);
         const double Bx = tot[0] / D, By = tot[1] / D, Bz = tot[2] / D;
+        if constexpr (TAN) {
+          const double tBx = tot[3 % NP] / D, tBy = tot[4 % NP] / D, tBz = tot[5 % NP] / D;
+          for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
+            if (e < n && part(e)) {
+              const double we = M.w[e];
+              M.tx[e] -= tBx * we;
+              M.ty[e] -= tBy * we;
+              M.tz[e] -= tBz * we;
+            }
+          });
+        }
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
                     if (e < n && part(e)) {
             const double we = M.w[e];
@@ -701,13 +869,18 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       }
       // energy violation, Eq. (18) (difference form), and the sums of Eq. (24)
       double dEs0, dEs1;
+      double tdEs0 = 0.0, tdEs1 = 0.0;  // tangent form
       {
         // per particle: the energy change (difference form, summed with
         // compensation: its total is a small difference of large terms and
         // decides how many pairs the correction uses) and, for an
         // inter-species collision, the kinetic energy of each species
         double es = 0.0, ec = 0.0;
-        double Ev[2] = {0.0, 0.0};
+        // KE_a, KE_b; tangent form: then the tangents of dE, KE_a, KE_b
+        constexpr int NE = TAN ? 5 : 2;
+        double Ev[NE];
+#pragma unroll
+        for (int i = 0; i < NE; ++i) Ev[i] = 0.0;
         const double c2 = A.c * A.c;
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
           if (e < n && part(e)) {
@@ -732,10 +905,35 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
               Ev[0] += ke;
             else
               Ev[1] += ke;
+            if constexpr (TAN) {
+              const double tvx = M.tx[e], tvy = M.ty[e], tvz = M.tz[e];
+              const double dke = mp * (vx * tvx + vy * tvy + vz * tvz);
+              Ev[2 % NE] += dke - mp * (ox * M.btx[e] + oy * M.bty[e] + oz * M.btz[e]);
+              if (isa)
+                Ev[3 % NE] += dke;
+              else
+                Ev[4 % NE] += dke;
+            }
           }
         });
         dEs1 = 0.0;
-        if (intra) {
+        if constexpr (TAN) {
+          double tot[NE];
+          block_sum_c1<TPC, NE>(es, ec, Ev, red, dEs0, tot);
+          tdEs0 = tot[2 % NE];
+          tdEs1 = 0.0;
+          if (!intra && dEs0 != 0.0) {
+            const double dE = dEs0, tdE = tot[2 % NE];
+            const double ea = s_sw[a] / na * tot[0], eb = s_sw[b] / nb * tot[1];
+            const double tea = s_sw[a] / na * tot[3 % NE], teb = s_sw[b] / nb * tot[4 % NE];
+            const double ra = ea / (ea + eb), rb = eb / (ea + eb);
+            const double tr = (tea * eb - ea * teb) / ((ea + eb) * (ea + eb));
+            dEs0 = ra * dE;
+            dEs1 = rb * dE;
+            tdEs0 = tr * dE + ra * tdE;
+            tdEs1 = -tr * dE + rb * tdE;
+          }
+        } else if (intra) {
           double tot[1];
           block_sum_c1<TPC, 1>(es, ec, Ev, red, dEs0, tot);
         } else {
@@ -768,6 +966,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       const int base1 = na / 2;           // pair slots of the second species
       double *Xb = Kb + CAP / 2;          // REL: h(-mu_R) per pair
       double resid0 = dEs0, resid1 = dEs1;
+      double tresid0 = tdEs0, tresid1 = tdEs1;  // tangent form
       int used_total = 0;
       for (int pass = 0; pass < A.max_passes; ++pass) {
         if (resid0 == 0.0 && resid1 == 0.0) break;
@@ -793,6 +992,12 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
             Xb[slot] = R.h0(-R.mu(), dh);
           } else {
             Kb[slot] = pair_K_nr(m1, m2, M.vx[p], M.vy[p], M.vz[p], M.vx[q], M.vy[q], M.vz[q]);
+            if constexpr (TAN) {
+              const double mu = m1 * m2 / (m1 + m2);
+              M.kdot[slot] = mu * ((M.vx[p] - M.vx[q]) * (M.tx[p] - M.tx[q]) +
+                                   (M.vy[p] - M.vy[q]) * (M.ty[p] - M.ty[q]) +
+                                   (M.vz[p] - M.vz[q]) * (M.tz[p] - M.tz[q]));
+            }
           }
         }
         __syncthreads();
@@ -837,6 +1042,9 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
             const double sgn = E0 < 0.0 ? -1.0 : 1.0;
             const int np = (s2 == 0 ? na : nb) / 2, kb = s2 == 0 ? 0 : base1;
             double absE = fabs(E0);
+            // tangent form: tangent of |E| (the cut pair's U is |E| minus the
+            // prefix before it; the others take f_E K)
+            double tabsE = TAN ? sgn * (s2 == 0 ? tresid0 : tresid1) : 0.0;
             int ncut = 0, used = 0;
             for (int m0 = 0; m0 < np && absE != 0.0; m0 += WAVE) {
               const int m = m0 + lane;
@@ -849,19 +1057,39 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
               }
               double Pprev = __shfl_up(P, 1);
               if (lane == 0) Pprev = 0.0;
+              double tlim = 0.0, tP = 0.0, tPprev = 0.0;
+              if constexpr (TAN) {
+                tlim = m < np ? A.fE * M.kdot[kb + m] : 0.0;
+                tP = tlim;
+#pragma unroll
+                for (int d = 1; d < WAVE; d <<= 1) {
+                  const double y = __shfl_up(tP, d);
+                  if (lane >= d) tP += y;
+                }
+                tPprev = __shfl_up(tP, 1);
+                if (lane == 0) tPprev = 0.0;
+              }
               const unsigned long long hit = __ballot(m < np && P >= absE);
               if (hit) {
                 const int kc = __builtin_ctzll(hit);
                 const double U = lane < kc ? lim : absE - Pprev;
                 if (lane <= kc) Kb[kb + m] = sgn * U;
+                if constexpr (TAN) {
+                  if (lane <= kc) M.kdot[kb + m] = sgn * (lane < kc ? tlim : tabsE - tPprev);
+                }
                 used += __popcll(__ballot(lane <= kc && U != 0.0));
                 ncut = m0 + kc + 1;
                 absE = 0.0;
+                tabsE = 0.0;
               } else {
                 if (m < np) Kb[kb + m] = sgn * lim;
+                if constexpr (TAN) {
+                  if (m < np) M.kdot[kb + m] = sgn * tlim;
+                }
                 used += __popcll(__ballot(m < np && lim != 0.0));
                 const int last = (np - m0 < WAVE ? np - m0 : WAVE) - 1;
                 absE -= __shfl(P, last);
+                if constexpr (TAN) tabsE -= __shfl(tP, last);
                 ncut = m0 + last + 1;
               }
             }
@@ -869,6 +1097,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
               s_ncut[s2] = ncut;
               s_res[s2] = sgn * absE;
               s_used[s2] = used;
+              if constexpr (TAN) s_tres[s2] = sgn * tabsE;
             }
           };
           if constexpr (NW > 1) {
@@ -881,6 +1110,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         if (nsl == 1 && t == 0) {
           s_ncut[1] = 0;
           s_res[1] = 0.0;
+          s_tres[1] = 0.0;
           s_used[1] = 0;
         }
         __syncthreads();
@@ -915,6 +1145,21 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
             const double x = U / K;
             const double g = -x / (1.0 + sqrt(1.0 - x));
             const double f1 = mu / m1 * g, f2 = mu / m2 * g;
+            if constexpr (TAN) {
+              // g = sqrt(1 - x) - 1, x = U / K
+              const double trx = M.tx[p] - M.tx[q], try_ = M.ty[p] - M.ty[q],
+                           trz = M.tz[p] - M.tz[q];
+              const double tK = mu * (rx * trx + ry * try_ + rz * trz);
+              const double tx_ = (M.kdot[slot] - x * tK) / K;
+              const double tg = -0.5 * tx_ / sqrt(1.0 - x);
+              const double c1 = mu / m1, c2 = mu / m2;
+              M.tx[p] += c1 * (tg * rx + g * trx);
+              M.ty[p] += c1 * (tg * ry + g * try_);
+              M.tz[p] += c1 * (tg * rz + g * trz);
+              M.tx[q] -= c2 * (tg * rx + g * trx);
+              M.ty[q] -= c2 * (tg * ry + g * try_);
+              M.tz[q] -= c2 * (tg * rz + g * trz);
+            }
             M.vx[p] += f1 * rx;
             M.vy[p] += f1 * ry;
             M.vz[p] += f1 * rz;
@@ -925,6 +1170,10 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         }
         resid0 = s_res[0];
         resid1 = s_res[1];
+        if constexpr (TAN) {
+          tresid0 = s_tres[0];
+          tresid1 = s_tres[1];
+        }
         used_total += s_used[0] + s_used[1];
         __syncthreads();
       }
@@ -940,11 +1189,16 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
             M.vx[e] = SNAPX(j, e);
             M.vy[e] = SNAPY(j, e);
             M.vz[e] = SNAPZ(j, e);
+            if constexpr (TAN) {
+              M.tx[e] = M.btx[e];
+              M.ty[e] = M.bty[e];
+              M.tz[e] = M.btz[e];
+            }
           }
         });
       }
       __syncthreads();
-      if (A.diag) {  // residual momentum and energy of this collision
+      if (!TAN && A.diag) {  // residual momentum and energy of this collision
         CSum<6> D;
         D.zero();
         const double c2 = A.c * A.c;
@@ -988,9 +1242,16 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
     MCC_PHASE(9);  // write-back
     __syncthreads();
     for (int e = t; e < n; e += TPC) {
-      A.vx[cb + e] = M.vx[e];
-      A.vy[cb + e] = M.vy[e];
-      A.vz[cb + e] = M.vz[e];
+      if (!TAN || A.write_primal) {
+        A.vx[cb + e] = M.vx[e];
+        A.vy[cb + e] = M.vy[e];
+        A.vz[cb + e] = M.vz[e];
+      }
+      if constexpr (TAN) {
+        A.tx[cb + e] = M.tx[e];
+        A.ty[cb + e] = M.ty[e];
+        A.tz[cb + e] = M.tz[e];
+      }
     }
     if (t == 0) {
       if (A.cell_corr) A.cell_corr[cell] = (int32_t)s_st[1];

@@ -42,6 +42,10 @@ struct CollideArgs {
   uint64_t big_stride;          // bytes per block
   unsigned long long *phase;    // profiling builds (MCC_PHASE_TIMING): clock ticks per phase
   const double2 *n97;           // N97 table: A and h dA/dt at the knots of t = ln s
+  // tangent (forward-mode) form only
+  double *tx, *ty, *tz;         // tangent of the velocities, in/out
+  double dlnl;                  // tangent of ln(Lambda) relative to ln(Lambda)
+  int32_t write_primal;         // 0: the velocities are read but not written back
 };
 
 }  // namespace mcc

@@ -6,7 +6,8 @@
 namespace mcc {
 
 // precision / physics modes compiled
-enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_REL = 2, NMODE = 3 };
+// MODE_TAN: FP64 step carrying the tangent of the velocities (forward mode)
+enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_REL = 2, MODE_TAN = 3, NMODE = 4 };
 
 // layout: 0 all in LDS; 1 compact LDS (weights read from the input);
 // 2 per-workgroup global scratch with one wave per cell
@@ -36,15 +37,25 @@ constexpr int kCandidates[NBUCKET][5] = {
     {0, 1, 2, -1, -1}, {1, 2, 3, 4, -1}, {3, 4, 5, 6, -1}, {5, 6, 7, 11, -1},
     {7, 11, 8, -1, -1}, {12, 13, 9, -1, -1}, {10, -1, -1, -1, -1}};
 
+// the tangent form keeps six more doubles per particle and one per pair: in
+// LDS up to 1024 particles, above that in global scratch
+constexpr Variant kTanVariantBig = {64, 4096, 2};
+
 inline constexpr Variant variant_of(int mode, int v) {
-  return (mode == MODE_REL && kVariants[v].layout == 1) ? kRelVariant4096 : kVariants[v];
+  return (mode == MODE_REL && kVariants[v].layout == 1) ? kRelVariant4096
+         : (mode == MODE_TAN && kVariants[v].cap > 1024 && kVariants[v].layout != 2)
+             ? kTanVariantBig
+             : kVariants[v];
 }
 
 // global scratch bytes per workgroup of a global-layout variant:
 // 8 CAP doubles (v, w, snapshot, pair buffer), 2 CAP u32 (keys, slots),
 // 6 CAP u16 (lists, orders, bucket members, weight order)
-constexpr unsigned long long big_stride_bytes(int cap) {
-  return ((unsigned long long)cap * (8 * 8 + 2 * 4 + 6 * 2) + 255ull) & ~255ull;
+// (tangent form: 7 more CAP doubles for the tangent, its snapshot and the
+// per-pair tangents)
+constexpr unsigned long long big_stride_bytes(int cap, bool tan = false) {
+  return ((unsigned long long)cap * (8 * 8 + 2 * 4 + 6 * 2 + (tan ? 7 * 8 : 0)) + 255ull) &
+         ~255ull;
 }
 
 }  // namespace mcc

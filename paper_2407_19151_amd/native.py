@@ -31,7 +31,8 @@ EXPORTS = ["mcc_default_params", "mcc_status_string", "mcc_create", "mcc_set_str
            "mcc_set_variant",
            "mcc_destroy", "mcc_device_error", "mcc_collide_sorted", "mcc_collide",
            "mcc_bin", "mcc_plan_create", "mcc_plan_run", "mcc_plan_describe",
-           "mcc_plan_destroy", "mcc_sample_angles", "mcc_plan_run_bucket"]
+           "mcc_plan_destroy", "mcc_sample_angles", "mcc_plan_run_bucket",
+           "mcc_collide_sorted_jvp"]
 
 
 class mcc_species(C.Structure):
@@ -100,6 +101,10 @@ def load(path: str = LIB_PATH):
     L.mcc_collide_sorted.restype = C.c_int
     L.mcc_collide.argtypes = [P, i64, P, P, i32, i32] + step_args
     L.mcc_collide.restype = C.c_int
+    L.mcc_collide_sorted_jvp.argtypes = [P, i64, i32, i32, P, P, P, P, P, P, P, P, P, f64,
+                                         C.POINTER(mcc_species), i32, C.POINTER(mcc_collision),
+                                         f64, f64, f64, u64, u64, C.POINTER(mcc_params), i32, P]
+    L.mcc_collide_sorted_jvp.restype = C.c_int
     L.mcc_bin.argtypes = [P, i64, P, P, i32, i32, P, P]
     L.mcc_bin.restype = C.c_int
     L.mcc_plan_create.argtypes = [P, C.POINTER(P), i64, i32, i32, P, P, P, P, P, P, f64,
@@ -176,11 +181,16 @@ def _ptr(t) -> Optional[int]:
 
 
 def _expect(t, dtype, n, name):
-    import torch
+    """Arguments handed to the library as raw pointers: right type and size,
+    dense, and on the GPU (the library reads them as flat device arrays)."""
     if t.dtype != dtype:
         raise TypeError("%s must be %s" % (name, dtype))
     if n is not None and t.numel() != n:
         raise ValueError("%s must have %d elements" % (name, n))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
 
 
 def _cur_stream():
@@ -263,6 +273,26 @@ class Context:
             _ptr(vz), cv, cvs, sp, len(collisions), co, float(dt), float(coulomb_log),
             int(seed), int(step), C.byref(p), _ptr(stats), _ptr(cell_corr_pairs))
         _check("mcc_collide_sorted", rc)
+
+    def collide_sorted_jvp(self, offsets, weights, vx, vy, vz, tx, ty, tz, *, n_cells: int,
+                           mass, charge, collisions, dt: float, coulomb_log: float,
+                           coulomb_log_tangent: float, seed: int, step: int,
+                           params: Optional[mcc_params] = None, cell_volume=1.0,
+                           update_primal: bool = True, stats=None):
+        """mcc_collide_sorted_jvp: the step and its tangent (tx, ty, tz in place)."""
+        import torch
+        n, cv, cvs, sp, co, p = self._common(weights, vx, vy, vz, cell_volume, mass, charge,
+                                             collisions, params, stats, None, n_cells)
+        _expect(offsets, torch.int64, n_cells * len(mass) + 1, "offsets")
+        for name, t in (("tx", tx), ("ty", ty), ("tz", tz)):
+            _expect(t, torch.float64, n, name)
+        self._stream()
+        rc = self.L.mcc_collide_sorted_jvp(
+            self.h, n, n_cells, len(mass), _ptr(offsets), _ptr(weights), _ptr(vx), _ptr(vy),
+            _ptr(vz), _ptr(tx), _ptr(ty), _ptr(tz), cv, cvs, sp, len(collisions), co, float(dt),
+            float(coulomb_log), float(coulomb_log_tangent), int(seed), int(step), C.byref(p),
+            int(bool(update_primal)), _ptr(stats))
+        _check("mcc_collide_sorted_jvp", rc)
 
     def collide(self, cells, species_id, weights, vx, vy, vz, *, n_cells: int, mass, charge,
                 collisions, dt: float, coulomb_log: float, seed: int, step: int,

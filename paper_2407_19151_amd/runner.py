@@ -56,6 +56,20 @@ def collide_sorted(ctx: native.Context, dw: DeviceWorkload, step: int,
                        cell_corr_pairs=dw.cell_corr if with_stats else None)
 
 
+def collide_sorted_jvp(ctx: native.Context, dw: DeviceWorkload, tangent, step: int,
+                       coulomb_log_tangent: float = 0.0,
+                       params: Optional[native.mcc_params] = None, update_primal: bool = True):
+    """One step of dw and its tangent; `tangent` is a (3, n) float64 device tensor,
+    updated in place."""
+    wl = dw.wl
+    ctx.collide_sorted_jvp(dw.offsets, dw.w, dw.vx, dw.vy, dw.vz, tangent[0], tangent[1],
+                           tangent[2], n_cells=wl.n_cells, mass=wl.mass, charge=wl.charge,
+                           collisions=wl.collisions, dt=wl.dt, coulomb_log=wl.coulomb_log,
+                           coulomb_log_tangent=coulomb_log_tangent, seed=wl.seed, step=step,
+                           params=params if params is not None else params_for(wl),
+                           cell_volume=wl.cell_volume, update_primal=update_primal)
+
+
 def collide_unsorted(ctx: native.Context, dw: DeviceWorkload, step: int,
                      params: Optional[native.mcc_params] = None):
     wl = dw.wl
