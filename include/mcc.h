@@ -238,7 +238,11 @@ mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells,
  * candidates on this population; 0 uses the built-in table), and captures
  * one step into a HIP graph.  mcc_plan_run replays it n_steps times with
  * steps first_step, first_step+1, ...  The plan holds the offsets and the
- * weights by pointer: if they change, destroy and re-create it.
+ * weights by pointer: if they change, destroy and re-create it.  With the
+ * moment correction on, it also computes once what depends on the weights
+ * alone (per cell and species: sum w, sum w^2, the weight range, and the
+ * descending-weight order of Algorithm 1), owning 40 B per (cell, species)
+ * and 2 B per particle of device memory for it.
  */
 mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n,
                            int32_t n_cells, int32_t n_species,

@@ -113,6 +113,7 @@ struct mcc_plan {
   int32_t n_cells = 0;
   int variant[NBUCKET] = {};
   DevBuf lists, counts, step;
+  DevBuf prep, prep_word;  // weight data of the bound population (PREP_READ)
   mcc_stats *stats = nullptr;
   int32_t *cell_corr = nullptr;
   hipGraph_t graph = nullptr;
@@ -698,6 +699,33 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
       mcc_plan_destroy(pl);
       return MCC_ERR_OOM;
     }
+  // the weights are bound to the plan: their per-(cell, species) sums, range
+  // and class, and the descending-weight order, are computed once here (with
+  // the chosen variants, so the sums round as in a step) and read by every
+  // step
+  if (p->moment_correction && n_cells > 0) {
+    if (!pl->prep.ensure(sizeof(SpeciesPrep) * (size_t)n_cells * n_species) ||
+        !pl->prep_word.ensure(sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1))) {
+      mcc_plan_destroy(pl);
+      return MCC_ERR_OOM;
+    }
+    CollideArgs W = pl->args;
+    W.prep_mode = PREP_WRITE;
+    W.prep = pl->prep.as<SpeciesPrep>();
+    W.prep_word = pl->prep_word.as<uint16_t>();
+    W.stats = nullptr;
+    W.cell_corr = nullptr;
+    st = launch_buckets(ctx, W, pl->mode, n_cells, pl->lists.as<int32_t>(),
+                        pl->counts.as<uint32_t>(), pl->variant, s);
+    if (st == MCC_OK) st = from_hip(hipStreamSynchronize(s));
+    if (st != MCC_OK) {
+      mcc_plan_destroy(pl);
+      return st;
+    }
+    pl->args.prep_mode = PREP_READ;
+    pl->args.prep = W.prep;
+    pl->args.prep_word = W.prep_word;
+  }
   // capture one step into a graph: stats reset, bucket kernels, step += 1
   hipStream_t cs;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -778,6 +806,8 @@ void mcc_plan_destroy(mcc_plan *pl) {
   pl->lists.release();
   pl->counts.release();
   pl->step.release();
+  pl->prep.release();
+  pl->prep_word.release();
   delete pl;
 }
 

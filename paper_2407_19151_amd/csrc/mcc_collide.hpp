@@ -662,7 +662,21 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       }
     }
     __syncthreads();
-    if (A.corr) {
+    if (A.corr && A.prep_mode == PREP_READ) {
+      // the plan's weight data of this cell
+      if (t < S) {
+        const SpeciesPrep P = A.prep[(int64_t)cell * S + t];
+        s_sw[t] = P.sw;
+        s_sw2[t] = P.sw2;
+        s_wlo[t] = P.lo;
+        s_whi[t] = P.hi;
+        s_wflag[t] = P.flag;
+      }
+      if constexpr (LAY != LAYOUT_COMPACT) {
+        for (int e = t; e < n; e += TPC) M.word[e] = A.prep_word[cb + e];
+      }
+      __syncthreads();
+    } else if (A.corr) {
       // per species, once per cell: sum w and sum w^2 (the denominator of
       // Eq. (17) and the mean weights of Eq. (24)), the weight range, and
       // for unequal weights the descending-weight order, which is the
@@ -700,9 +714,20 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
           s_wlo[sp] = lo[0];
           s_whi[sp] = hi[0];
           s_wflag[sp] = flag;
+          if (A.prep_mode == PREP_WRITE)
+            A.prep[(int64_t)cell * S + sp] = SpeciesPrep{tot[0], tot[1], lo[0], hi[0], flag, 0};
         }
       }
       __syncthreads();
+      if (A.prep_mode == PREP_WRITE) {
+        if constexpr (LAY != LAYOUT_COMPACT) {
+          for (int e = t; e < n; e += TPC) A.prep_word[cb + e] = M.word[e];
+        }
+      }
+    }
+    if (A.prep_mode == PREP_WRITE) {  // weight data only: no step
+      __syncthreads();
+      continue;
     }
 
     for (int k = 0; k < A.n_coll; ++k) {

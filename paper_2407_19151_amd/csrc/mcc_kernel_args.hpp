@@ -19,6 +19,19 @@ struct CollConst {
   double fa, fb;  // m_b/(m_a+m_b), m_a/(m_a+m_b): shares of du (Eq. (8) masses)
 };
 
+// Per (cell, species) data that depends on the weights only, computed once
+// by a plan and read by every step: sum w, sum w^2, the weight range (bit
+// patterns) and the weight class (equal / distinct / ties)
+struct SpeciesPrep {
+  double sw, sw2;
+  uint64_t lo, hi;
+  int32_t flag;
+  int32_t pad;
+};
+
+// prep_mode of CollideArgs
+enum : int32_t { PREP_NONE = 0, PREP_WRITE = 1, PREP_READ = 2 };
+
 struct CollideArgs {
   const int64_t *offsets;  // [n_cells*S + 1]
   const double *w;
@@ -46,6 +59,12 @@ struct CollideArgs {
   double *tx, *ty, *tz;         // tangent of the velocities, in/out
   double dlnl;                  // tangent of ln(Lambda) relative to ln(Lambda)
   int32_t write_primal;         // 0: the velocities are read but not written back
+  // weight data of a plan: PREP_WRITE computes it and skips the step,
+  // PREP_READ uses it (prep[n_cells*S], prep_word[n]: descending-weight
+  // order, cell-local)
+  int32_t prep_mode;
+  SpeciesPrep *prep;
+  uint16_t *prep_word;
 };
 
 }  // namespace mcc
