@@ -20,6 +20,9 @@ const void *const *mcc_kernel_table_fp64();
 const void *const *mcc_kernel_table_fp32();
 const void *const *mcc_kernel_table_rel();
 const void *const *mcc_kernel_table_tan();
+const void *const *mcc_kernel_table_fp64_diag();
+const void *const *mcc_kernel_table_fp32_diag();
+const void *const *mcc_kernel_table_rel_diag();
 
 namespace mcc {
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -86,6 +89,9 @@ const void *const *kernel_table(int mode) {
     case MODE_FP64: return mcc_kernel_table_fp64();
     case MODE_FP32: return mcc_kernel_table_fp32();
     case MODE_TAN: return mcc_kernel_table_tan();
+    case MODE_FP64_DIAG: return mcc_kernel_table_fp64_diag();
+    case MODE_FP32_DIAG: return mcc_kernel_table_fp32_diag();
+    case MODE_REL_DIAG: return mcc_kernel_table_rel_diag();
     default: return mcc_kernel_table_rel();
   }
 }
@@ -135,9 +141,12 @@ mcc_status from_hip(hipError_t e) {
     if (e_ != hipSuccess) return from_hip(e_); \
   } while (0)
 
-int mode_of(const mcc_params *p) {
-  if (p->relativistic) return MODE_REL;
-  return p->precision == MCC_FP32_KINEMATICS ? MODE_FP32 : MODE_FP64;
+// kernel family of a step: precision / physics, and whether diagnostics are
+// measured (A.diag, set by fill_args)
+int mode_of(const mcc_params *p, const CollideArgs &A) {
+  if (p->relativistic) return A.diag ? MODE_REL_DIAG : MODE_REL;
+  if (p->precision == MCC_FP32_KINEMATICS) return A.diag ? MODE_FP32_DIAG : MODE_FP32;
+  return A.diag ? MODE_FP64_DIAG : MODE_FP64;
 }
 
 // host checks of the step arguments shared by every entry point
@@ -457,7 +466,7 @@ mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t 
   if (n_cells == 0) return finish(ctx);
   HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, ctx->lists.as<int32_t>(),
                               ctx->counts.as<uint32_t>(), cell_corr_pairs, ctx->err, s));
-  st = launch_buckets(ctx, A, mode_of(p), n_cells, ctx->lists.as<int32_t>(),
+  st = launch_buckets(ctx, A, mode_of(p, A), n_cells, ctx->lists.as<int32_t>(),
                       ctx->counts.as<uint32_t>(), ctx->variant, s);
   if (st != MCC_OK) return st;
   return finish(ctx);
@@ -603,7 +612,6 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
   HIP_TRY(hipSetDevice(ctx->device));
   mcc_plan *pl = new mcc_plan();
   pl->ctx = ctx;
-  pl->mode = mode_of(p);
   pl->n_cells = n_cells;
   pl->stats = stats;
   pl->cell_corr = cell_corr_pairs;
@@ -615,6 +623,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
   fill_args(pl->args, n, n_cells, n_species, offsets, weights, vx, vy, vz, cell_volume,
             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, seed, 0, p, stats,
             cell_corr_pairs, ctx->err, ctx->n97.as<double2>());
+  pl->mode = mode_of(p, pl->args);
   pl->args.step_dev = pl->step.as<uint64_t>();
   hipStream_t s = ctx->stream;
   // device work lists, built once (offsets are fixed for the plan)
@@ -711,6 +720,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
     }
     CollideArgs W = pl->args;
     W.prep_mode = PREP_WRITE;
+    W.n_coll = 0;  // weight data only: no collision is applied (velocities unchanged)
     W.prep = pl->prep.as<SpeciesPrep>();
     W.prep_word = pl->prep_word.as<uint16_t>();
     W.stats = nullptr;

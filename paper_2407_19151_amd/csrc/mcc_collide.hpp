@@ -477,7 +477,7 @@ __device__ __forceinline__ void for_owned(int n, F &&f) {
 // ---------------------------------------------------------------------------
 // The kernel
 // ---------------------------------------------------------------------------
-template <int TPC, int CAP, typename KR, bool REL, int LAY, bool TAN = false>
+template <int TPC, int CAP, typename KR, bool REL, int LAY, bool TAN = false, bool DIAG = false>
 __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
   constexpr int PPT = CAP / TPC;
   constexpr int NW = TPC / WAVE;
@@ -486,8 +486,8 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
   static_assert(CAP % TPC == 0 && TPC % WAVE == 0, "bad variant");
   static_assert(!(REL && LAY == LAYOUT_COMPACT), "REL needs the full pair buffer");
   static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
-  static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT),
-                "the tangent form is FP64 non-relativistic");
+  static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT && !DIAG),
+                "the tangent form is FP64 non-relativistic, without diagnostics");
   __shared__ double red[2 * 6 * NW];
   uint64_t *redu = reinterpret_cast<uint64_t *>(red);
   __shared__ uint32_t wsum[NW];
@@ -724,10 +724,6 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
           for (int e = t; e < n; e += TPC) A.prep_word[cb + e] = M.word[e];
         }
       }
-    }
-    if (A.prep_mode == PREP_WRITE) {  // weight data only: no step
-      __syncthreads();
-      continue;
     }
 
     for (int k = 0; k < A.n_coll; ++k) {
@@ -1223,7 +1219,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         });
       }
       __syncthreads();
-      if (!TAN && A.diag) {  // residual momentum and energy of this collision
+      if constexpr (DIAG) {  // residual momentum and energy of this collision
         CSum<6> D;
         D.zero();
         const double c2 = A.c * A.c;

@@ -59,9 +59,9 @@ struct CollideArgs {
   double *tx, *ty, *tz;         // tangent of the velocities, in/out
   double dlnl;                  // tangent of ln(Lambda) relative to ln(Lambda)
   int32_t write_primal;         // 0: the velocities are read but not written back
-  // weight data of a plan: PREP_WRITE computes it and skips the step,
-  // PREP_READ uses it (prep[n_cells*S], prep_word[n]: descending-weight
-  // order, cell-local)
+  // weight data of a plan: PREP_WRITE computes and stores it (launched with
+  // no collisions), PREP_READ uses it (prep[n_cells*S], prep_word[n]:
+  // descending-weight order, cell-local)
   int32_t prep_mode;
   SpeciesPrep *prep;
   uint16_t *prep_word;

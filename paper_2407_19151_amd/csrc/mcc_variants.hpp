@@ -6,8 +6,19 @@
 namespace mcc {
 
 // precision / physics modes compiled
-// MODE_TAN: FP64 step carrying the tangent of the velocities (forward mode)
-enum Mode { MODE_FP64 = 0, MODE_FP32 = 1, MODE_REL = 2, MODE_TAN = 3, NMODE = 4 };
+// MODE_TAN: FP64 step carrying the tangent of the velocities (forward mode);
+// the *_DIAG modes also measure the residual momentum and energy (separate
+// kernels, so the step without diagnostics carries none of their registers)
+enum Mode {
+  MODE_FP64 = 0,
+  MODE_FP32 = 1,
+  MODE_REL = 2,
+  MODE_TAN = 3,
+  MODE_FP64_DIAG = 4,
+  MODE_FP32_DIAG = 5,
+  MODE_REL_DIAG = 6,
+  NMODE = 7
+};
 
 // layout: 0 all in LDS; 1 compact LDS (weights read from the input);
 // 2 per-workgroup global scratch with one wave per cell
@@ -42,7 +53,8 @@ constexpr int kCandidates[NBUCKET][5] = {
 constexpr Variant kTanVariantBig = {64, 4096, 2};
 
 inline constexpr Variant variant_of(int mode, int v) {
-  return (mode == MODE_REL && kVariants[v].layout == 1) ? kRelVariant4096
+  return ((mode == MODE_REL || mode == MODE_REL_DIAG) && kVariants[v].layout == 1)
+             ? kRelVariant4096
          : (mode == MODE_TAN && kVariants[v].cap > 1024 && kVariants[v].layout != 2)
              ? kTanVariantBig
              : kVariants[v];
