@@ -478,13 +478,17 @@ __device__ __forceinline__ void for_owned(int n, F &&f) {
 // The kernel
 // ---------------------------------------------------------------------------
 template <int TPC, int CAP, typename KR, bool REL, int LAY, bool TAN = false, bool DIAG = false>
-__global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
+__global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8, TAN))
+    collide_kernel(CollideArgs A) {
   constexpr int PPT = CAP / TPC;
   constexpr int NW = TPC / WAVE;
   constexpr bool GL = LAY == LAYOUT_GLOBAL;
   constexpr bool BIG = GL;  // snapshot in memory, runtime owner loops
   static_assert(CAP % TPC == 0 && TPC % WAVE == 0, "bad variant");
   static_assert(!(REL && LAY == LAYOUT_COMPACT), "REL needs the full pair buffer");
+  // the descending-weight order has an LDS home except in the 4096 compact
+  // layout (no room); there a plan's order is read from HBM
+  constexpr bool HAS_WORD = LAY != LAYOUT_COMPACT || CAP <= 2048;
   static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
   static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT && !DIAG),
                 "the tangent form is FP64 non-relativistic, without diagnostics");
@@ -561,7 +565,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
     }
   } else if constexpr (LAY == LAYOUT_COMPACT) {
     __shared__ double lv[3 * CAP];
-    __shared__ __attribute__((aligned(16))) uint16_t lidx[5 * CAP];
+    __shared__ __attribute__((aligned(16))) uint16_t lidx[(HAS_WORD ? 6 : 5) * CAP];
     M.vx = lv;
     M.vy = lv + CAP;
     M.vz = lv + 2 * CAP;
@@ -574,7 +578,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
     // energies live in the bucket counters (dead after the weight order)
     M.key = reinterpret_cast<uint32_t *>(lidx + 2 * CAP);
     M.kbuf = reinterpret_cast<double *>(lcnt);
-    M.word = M.mem;  // unused: no room here, species with unequal weights sort per collision
+    M.word = HAS_WORD ? lidx + 5 * CAP : M.list0;  // (list0: scratch of the plan's weight pass)
   } else {
     char *base = A.big_scratch + (uint64_t)blockIdx.x * A.big_stride;
     double *dv = reinterpret_cast<double *>(base);
@@ -672,7 +676,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         s_whi[t] = P.hi;
         s_wflag[t] = P.flag;
       }
-      if constexpr (LAY != LAYOUT_COMPACT) {
+      if constexpr (HAS_WORD) {
         for (int e = t; e < n; e += TPC) M.word[e] = A.prep_word[cb + e];
       }
       __syncthreads();
@@ -699,7 +703,9 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         int flag = WORDER_EQUAL;
         if (A.sortw && ns >= 2 && lo[0] != hi[0]) {
           flag = WORDER_TIES;
-          if constexpr (LAY != LAYOUT_COMPACT) {
+          // without an LDS home the order is kept only by a plan's weight
+          // pass (M.word is list0 then, free before any collision)
+          if (HAS_WORD || A.prep_mode == PREP_WRITE) {
             weight_sort<TPC, PPT, GL>(M, ns, nullptr, o, M.word + o, lo[0], hi[0], wsum,
                                       &maxocc);
             int tie = 0;
@@ -720,9 +726,7 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       }
       __syncthreads();
       if (A.prep_mode == PREP_WRITE) {
-        if constexpr (LAY != LAYOUT_COMPACT) {
-          for (int e = t; e < n; e += TPC) A.prep_word[cb + e] = M.word[e];
-        }
+        for (int e = t; e < n; e += TPC) A.prep_word[cb + e] = M.word[e];
       }
     }
 
@@ -845,7 +849,9 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
       };
       auto mass_of = [&](int e) { return (e >= oa && e < oa + na) ? ma : mb; };
 
-      // momentum restore, Eq. (17): B = sum m_p (v_ps - v_bs) / sum m_p w_p
+      // momentum restore, Eq. (17): B = sum m_p (v_ps - v_bs) / sum m_p w_p;
+      // v -= B w is applied in the energy pass below
+      double Bx, By, Bz;
       {
         constexpr int NP = TAN ? 6 : 3;  // the tangent of the sums rides along
         double P[NP];
@@ -867,7 +873,9 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         double tot[NP];
         block_sum<TPC, NP>(P, red, tot);
         const double D = ma * s_sw2[a] + (intra ? 0.0 : mb * s_sw2[b]);
-        const double Bx = tot[0] / D, By = tot[1] / D, Bz = tot[2] / D;
+        Bx = tot[0] / D;
+        By = tot[1] / D;
+        Bz = tot[2] / D;
         if constexpr (TAN) {
           const double tBx = tot[3 % NP] / D, tBy = tot[4 % NP] / D, tBz = tot[5 % NP] / D;
           for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
@@ -879,14 +887,6 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
             }
           });
         }
-        for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
-                    if (e < n && part(e)) {
-            const double we = M.w[e];
-            M.vx[e] -= Bx * we;
-            M.vy[e] -= By * we;
-            M.vz[e] -= Bz * we;
-          }
-        });
       }
       // energy violation, Eq. (18) (difference form), and the sums of Eq. (24)
       double dEs0, dEs1;
@@ -906,8 +906,12 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
           if (e < n && part(e)) {
             const bool isa = e >= oa && e < oa + na;
-            const double mp = (isa ? ma : mb) * M.w[e];
-            const double vx = M.vx[e], vy = M.vy[e], vz = M.vz[e];
+            const double we = M.w[e];
+            const double mp = (isa ? ma : mb) * we;
+            const double vx = M.vx[e] - Bx * we, vy = M.vy[e] - By * we, vz = M.vz[e] - Bz * we;
+            M.vx[e] = vx;
+            M.vy[e] = vy;
+            M.vz[e] = vz;
             const double ox = SNAPX(j, e), oy = SNAPY(j, e), oz = SNAPZ(j, e);
             const double dd = (vx - ox) * (vx + ox) + (vy - oy) * (vy + oy) + (vz - oz) * (vz + oz);
             double term, ke;
@@ -976,7 +980,14 @@ __global__ void __launch_bounds__(TPC) collide_kernel(CollideArgs A) {
         auto order = [&](int sp, int o, int ns, const uint16_t *L, uint16_t *ord) {
           const int f = s_wflag[sp];
           if (f == WORDER_EQUAL) return L;  // all weights equal: the shuffled order
-          if (LAY != LAYOUT_COMPACT && f == WORDER_DISTINCT) return (const uint16_t *)(M.word + o);
+          if (f == WORDER_DISTINCT) {
+            // (without an LDS home: only a plan marks a species distinct, and
+            // its order is read from HBM)
+            if constexpr (HAS_WORD)
+              return (const uint16_t *)(M.word + o);
+            else
+              return (const uint16_t *)(A.prep_word + cb + o);
+          }
           weight_sort<TPC, PPT, GL>(M, ns, L, 0, ord, s_wlo[sp], s_whi[sp], wsum, &maxocc);
           return (const uint16_t *)ord;
         };

@@ -52,12 +52,35 @@ constexpr int kCandidates[NBUCKET][5] = {
 // LDS up to 1024 particles, above that in global scratch
 constexpr Variant kTanVariantBig = {64, 4096, 2};
 
+// The FP64 and FP32 modes run every LDS variant in the compact layout
+// (weights read from HBM, keys and pair energies aliased: 40-42 B of LDS per
+// particle of capacity instead of 56, so more cells are resident per CU); the
+// relativistic and tangent modes keep the full layout.
+inline constexpr Variant compact_of(Variant V) {
+  return V.layout == 0 ? Variant{V.tpc, V.cap, 1} : V;
+}
+
 inline constexpr Variant variant_of(int mode, int v) {
   return ((mode == MODE_REL || mode == MODE_REL_DIAG) && kVariants[v].layout == 1)
              ? kRelVariant4096
          : (mode == MODE_TAN && kVariants[v].cap > 1024 && kVariants[v].layout != 2)
              ? kTanVariantBig
+         : (mode == MODE_FP64 || mode == MODE_FP32 || mode == MODE_FP64_DIAG ||
+            mode == MODE_FP32_DIAG)
+             ? compact_of(kVariants[v])
              : kVariants[v];
+}
+
+// Minimum waves per SIMD the compiler must leave room for (it then caps the
+// registers, spilling a little): measured on the lognormal cell-size mix,
+// where 2 waves per SIMD (the uncapped allocation) left the cell kernels
+// waiting on LDS and barriers most of the time.  1: no cap (variants whose
+// LDS use already limits residency, the global-scratch and tangent forms).
+constexpr int min_waves(int tpc, int cap, int layout, bool fp64, bool tangent) {
+  if (tangent || layout == 2 || cap >= 2048) return 1;
+  if (tpc == 64 && cap == 128) return 4;
+  if (tpc == 128 && cap == 512) return fp64 ? 3 : 4;
+  return 3;
 }
 
 // global scratch bytes per workgroup of a global-layout variant:
