@@ -129,7 +129,9 @@ mcc_status mcc_device_error(mcc_ctx *ctx, int32_t *code);
  * 4 (256,512), 5 (256,1024), 6 (512,1024), 7 (512,2048), 8 (1024,2048),
  * 9 (1024,4096), 10 (64,32768, one wave with global scratch), 11 (256,2048),
  * 12 (512,4096), 13 (256,4096); in relativistic mode 9, 12 and 13 run as
- * (64,4096) with global scratch.  -1 restores the default.  The variant's capacity must hold the bucket's largest cell,
+ * (64,4096) with global scratch.  -1 restores the default, which depends on
+ * the precision mode (built-in table, the fastest measured on lognormal
+ * cell-size mixes).  The variant's capacity must hold the bucket's largest cell,
  * else MCC_ERR_INVALID.  Results agree between variants to rounding (the
  * order of the per-cell sums depends on the threads per cell).
  */

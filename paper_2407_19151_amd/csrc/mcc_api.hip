@@ -284,8 +284,8 @@ mcc_status launch_buckets(mcc_ctx *ctx, const CollideArgs &base, int mode, int32
                           const int32_t *lists, const uint32_t *counts, const int *variant,
                           hipStream_t stream) {
   for (int b = NBUCKET - 1; b >= 0; --b) {
-    const mcc_status st =
-        launch_bucket(ctx, base, mode, n_cells, lists, counts, b, variant[b], stream);
+    const int v = variant[b] >= 0 ? variant[b] : default_variant(mode, b);
+    const mcc_status st = launch_bucket(ctx, base, mode, n_cells, lists, counts, b, v, stream);
     if (st != MCC_OK) return st;
   }
   return MCC_OK;
@@ -361,7 +361,7 @@ mcc_status mcc_create(mcc_ctx **out, int device, void *hip_stream) {
     return from_hip(e);
   }
   ctx->n_cu = prop.multiProcessorCount;
-  for (int b = 0; b < NBUCKET; ++b) ctx->variant[b] = kDefaultVariant[b];
+  for (int b = 0; b < NBUCKET; ++b) ctx->variant[b] = -1;  // the mode's default
   const char *val = std::getenv("MCC_VALIDATE");
   ctx->validate = val && val[0] == '1';
   e = hipMalloc(&ctx->err, sizeof(int32_t));
@@ -413,7 +413,7 @@ mcc_status mcc_set_variant(mcc_ctx *ctx, int32_t bucket, int32_t variant) {
   if (!ctx || bucket < 0 || bucket >= NBUCKET || variant < -1 || variant >= NVARIANT)
     return MCC_ERR_INVALID;
   if (variant == -1) {
-    ctx->variant[bucket] = kDefaultVariant[bucket];
+    ctx->variant[bucket] = -1;
     return MCC_OK;
   }
   if (kVariants[variant].cap < kBucketCap[bucket]) return MCC_ERR_INVALID;
@@ -615,7 +615,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
   pl->n_cells = n_cells;
   pl->stats = stats;
   pl->cell_corr = cell_corr_pairs;
-  for (int b = 0; b < NBUCKET; ++b) pl->variant[b] = kDefaultVariant[b];
+  for (int b = 0; b < NBUCKET; ++b) pl->variant[b] = -1;
   if (!ensure_lists(ctx, pl->lists, pl->counts, n_cells) || !pl->step.ensure(64)) {
     mcc_plan_destroy(pl);
     return MCC_ERR_OOM;
@@ -624,6 +624,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, seed, 0, p, stats,
             cell_corr_pairs, ctx->err, ctx->n97.as<double2>());
   pl->mode = mode_of(p, pl->args);
+  for (int b = 0; b < NBUCKET; ++b) pl->variant[b] = default_variant(pl->mode, b);
   pl->args.step_dev = pl->step.as<uint64_t>();
   hipStream_t s = ctx->stream;
   // device work lists, built once (offsets are fixed for the plan)

@@ -486,9 +486,10 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   constexpr bool BIG = GL;  // snapshot in memory, runtime owner loops
   static_assert(CAP % TPC == 0 && TPC % WAVE == 0, "bad variant");
   static_assert(!(REL && LAY == LAYOUT_COMPACT), "REL needs the full pair buffer");
-  // the descending-weight order has an LDS home except in the 4096 compact
-  // layout (no room); there a plan's order is read from HBM
-  constexpr bool HAS_WORD = LAY != LAYOUT_COMPACT || CAP <= 2048;
+  // the descending-weight order has an LDS home up to 1024 particles in the
+  // compact layout (above, its room would cost a second resident cell per
+  // CU); there a plan's order is read from HBM
+  constexpr bool HAS_WORD = LAY != LAYOUT_COMPACT || CAP <= 1024;
   static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
   static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT && !DIAG),
                 "the tangent form is FP64 non-relativistic, without diagnostics");

@@ -41,8 +41,10 @@ constexpr Variant kRelVariant4096 = {64, 4096, 2};
 constexpr int NBUCKET = 7;
 constexpr int kBucketCap[NBUCKET] = {128, 256, 512, 1024, 2048, 4096, 32768};
 // default variant per bucket (the fastest measured on lognormal cell-size
-// mixes; the autotuner may pick another candidate)
+// mixes; the autotuner may pick another candidate): FP32 kinematics take 256
+// threads for the 2048 bucket, FP64 (more registers per thread) 512
 constexpr int kDefaultVariant[NBUCKET] = {0, 1, 3, 5, 7, 12, 10};
+constexpr int kDefaultVariantFP32[NBUCKET] = {0, 1, 3, 5, 11, 12, 10};
 // candidates the autotuner times per bucket (-1 terminated)
 constexpr int kCandidates[NBUCKET][5] = {
     {0, 1, 2, -1, -1}, {1, 2, 3, 4, -1}, {3, 4, 5, 6, -1}, {5, 6, 7, 11, -1},
@@ -58,6 +60,11 @@ constexpr Variant kTanVariantBig = {64, 4096, 2};
 // relativistic and tangent modes keep the full layout.
 inline constexpr Variant compact_of(Variant V) {
   return V.layout == 0 ? Variant{V.tpc, V.cap, 1} : V;
+}
+
+inline constexpr int default_variant(int mode, int bucket) {
+  return (mode == MODE_FP32 || mode == MODE_FP32_DIAG) ? kDefaultVariantFP32[bucket]
+                                                         : kDefaultVariant[bucket];
 }
 
 inline constexpr Variant variant_of(int mode, int v) {
