@@ -413,6 +413,49 @@ __device__ __forceinline__ void shuffle_species(const CellMem &M, int ns, int of
   __syncthreads();
 }
 
+// The random permutations of both species of an inter-species collision in
+// one LDS sort: species a's items take buckets [0, na) and species b's
+// [na, na + nb), so items of different species are never compared and each
+// species comes out sorted by (Philox word, index) exactly as alone.
+// out[0..na) = species a, out[na..na+nb) = species b (cell-local indices).
+template <int TPC, int PPT, bool G>
+__device__ __forceinline__ void shuffle_two(const CellMem &M, int na, int oa, int nb, int ob,
+                                            uint32_t cell, uint32_t step_lo, uint32_t c3a,
+                                            uint32_t c3b, uint32_t k0, uint32_t k1,
+                                            uint16_t *out, uint32_t *wsum, uint32_t *maxocc) {
+  uint32_t *key = M.key;
+  const int t = threadIdx.x;
+  const int n = na + nb;
+  const int qa = (na + 3) >> 2;
+  for (int q = t; q < qa + ((nb + 3) >> 2); q += TPC) {
+    const bool sa = q < qa;
+    const int qq = sa ? q : q - qa;
+    const U4 r = philox((uint32_t)qq, cell, step_lo, sa ? c3a : c3b, k0, k1);
+    const int ns = sa ? na : nb;
+    const int i = 4 * qq;
+    uint32_t *kk = key + (sa ? 0 : na);
+    kk[i] = r.x;
+    if (i + 1 < ns) kk[i + 1] = r.y;
+    if (i + 2 < ns) kk[i + 2] = r.z;
+    if (i + 3 < ns) kk[i + 3] = r.w;
+  }
+  __syncthreads();
+  const uint64_t nau = (uint64_t)na, nbu = (uint64_t)nb;
+  bucket_rank_sort<TPC, PPT, G>(
+      n, M.cnt, M.mem, out, wsum, maxocc,
+      [&](int i) -> uint32_t {
+        return i < na ? (uint32_t)(((uint64_t)key[i] * nau) >> 32)
+                      : (uint32_t)na + (uint32_t)(((uint64_t)key[i] * nbu) >> 32);
+      },
+      [&](int o, int i) -> bool {
+        const uint32_t ko = key[o], ki = key[i];
+        return ko < ki || (ko == ki && o < i);
+      },
+      M.slotbuf);
+  for (int q = t; q < n; q += TPC) out[q] = (uint16_t)(out[q] + (q < na ? oa : ob - na));
+  __syncthreads();
+}
+
 // Descending-weight order of ns particles, stable in list position (Alg. 1,
 // optional step): the particles are L[0..ns) (cell-local indices), or, with
 // L == nullptr, off, off+1, ..., off+ns-1.  O receives cell-local indices.
@@ -766,12 +809,16 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
 #define SNAPZ(j, e) (BIG ? M.bz[e] : bz[BIG ? 0 : (j)])
 
       // random binary pairs (Fig. 1)
-      shuffle_species<TPC, PPT, GL>(M, na, oa, (uint32_t)cell, step_lo,
-                                ctr3(step, k, PURPOSE_SHUFFLE0 + 0), k0, k1, M.list0, wsum,
-                                &maxocc);
-      if (!intra)
-        shuffle_species<TPC, PPT, GL>(M, nb, ob, (uint32_t)cell, step_lo,
-                                  ctr3(step, k, PURPOSE_SHUFFLE0 + 1), k0, k1, M.list1, wsum,
+      // L0, L1: the shuffled lists of species a and b
+      const uint16_t *L0 = M.list0, *L1 = M.list0 + na;
+      if (intra)
+        shuffle_species<TPC, PPT, GL>(M, na, oa, (uint32_t)cell, step_lo,
+                                      ctr3(step, k, PURPOSE_SHUFFLE0 + 0), k0, k1, M.list0,
+                                      wsum, &maxocc);
+      else
+        shuffle_two<TPC, PPT, GL>(M, na, oa, nb, ob, (uint32_t)cell, step_lo,
+                                  ctr3(step, k, PURPOSE_SHUFFLE0 + 0),
+                                  ctr3(step, k, PURPOSE_SHUFFLE0 + 1), k0, k1, M.list0, wsum,
                                   &maxocc);
 
       // scatter (Sec. 3.2 pairing) in rounds of disjoint pairs:
@@ -797,7 +844,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
           uint32_t kp;
           double f = 1.0;
           if (intra) {
-            const uint16_t *L = M.list0;
+            const uint16_t *L = L0;
             if (odd) {
               if (sl == 0) {
                 I = L[r];
@@ -817,8 +864,8 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             }
           } else {
             const int kk = r * Nmin + sl;
-            I = abig ? M.list0[kk] : M.list0[sl];
-            J = abig ? M.list1[sl] : M.list1[kk];
+            I = abig ? L0[kk] : L0[sl];
+            J = abig ? L1[sl] : L1[kk];
             kp = (uint32_t)kk;
           }
           const double cf = C.coef * f * (nmin / dV);
@@ -976,7 +1023,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
 
       // correction order per species (Alg. 1, optional sort), then the pair loop
       const int nsl = intra ? 1 : 2;
-      const uint16_t *O0 = M.list0, *O1 = M.list1;
+      const uint16_t *O0 = L0, *O1 = L1;
       if (A.sortw) {
         auto order = [&](int sp, int o, int ns, const uint16_t *L, uint16_t *ord) {
           const int f = s_wflag[sp];
@@ -992,8 +1039,8 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
           weight_sort<TPC, PPT, GL>(M, ns, L, 0, ord, s_wlo[sp], s_whi[sp], wsum, &maxocc);
           return (const uint16_t *)ord;
         };
-        O0 = order(a, oa, na, M.list0, M.ord0);
-        if (!intra) O1 = order(b, ob, nb, M.list1, M.ord1);
+        O0 = order(a, oa, na, L0, M.ord0);
+        if (!intra) O1 = order(b, ob, nb, L1, M.ord1);
       }
       double *Kb = M.kbuf;
       const int base1 = na / 2;           // pair slots of the second species
