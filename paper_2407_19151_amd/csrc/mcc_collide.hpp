@@ -832,40 +832,41 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       const int Nmax = abig ? na : nb, Nmin = abig ? nb : na;
       const double nmin = intra ? (double)(na - 1) : (double)Nmin;
       const bool odd = intra && (na & 1);
-      const int nrounds = intra ? (odd ? 3 : 1) : (Nmax + Nmin - 1) / Nmin;
-      for (int r = 0; r < nrounds; ++r) {
-        int nslots;
-        if (intra)
-          nslots = odd ? (r == 0 ? 1 + (na - 3) / 2 : 1) : na / 2;
-        else
-          nslots = (Nmax - r * Nmin) < Nmin ? (Nmax - r * Nmin) : Nmin;
-        for (int sl = t; sl < nslots; sl += TPC) {
+      // Pairs that share a particle form a chain, run in order by one lane:
+      // the odd triple (L0,L1),(L1,L2),(L2,L0); in an inter-species collision
+      // the pairs k, k + N_min, k + 2 N_min, ... (they share small[k]).
+      // Different chains touch disjoint particles, so one barrier ends the
+      // scatter and every particle sees its pairs in ascending k.
+      const int nchains = intra ? (odd ? 1 + (na - 3) / 2 : na / 2) : Nmin;
+      for (int ch = t; ch < nchains; ch += TPC) {
+        const int len = intra ? ((odd && ch == 0) ? 3 : 1) : (Nmax - ch + Nmin - 1) / Nmin;
+        for (int r = 0; r < len; ++r) {
           int I, J;
           uint32_t kp;
           double f = 1.0;
           if (intra) {
             const uint16_t *L = L0;
             if (odd) {
-              if (sl == 0) {
+              if (ch == 0) {
                 I = L[r];
                 J = L[r == 2 ? 0 : r + 1];
                 kp = (uint32_t)r;
                 f = 0.5;
               } else {
-                const int m = sl - 1;
+                const int m = ch - 1;
                 I = L[3 + 2 * m];
                 J = L[4 + 2 * m];
                 kp = (uint32_t)(3 + m);
               }
             } else {
-              I = L[2 * sl];
-              J = L[2 * sl + 1];
-              kp = (uint32_t)sl;
+              I = L[2 * ch];
+              J = L[2 * ch + 1];
+              kp = (uint32_t)ch;
             }
           } else {
-            const int kk = r * Nmin + sl;
-            I = abig ? L0[kk] : L0[sl];
-            J = abig ? L1[sl] : L1[kk];
+            const int kk = r * Nmin + ch;
+            I = abig ? L0[kk] : L0[ch];
+            J = abig ? L1[ch] : L1[kk];
             kp = (uint32_t)kk;
           }
           const double cf = C.coef * f * (nmin / dV);
@@ -882,8 +883,8 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, C.fa, C.fb, A.method,
                                 (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
         }
-        __syncthreads();
       }
+      __syncthreads();
       if (t == 0) {
         s_st[0] += intra ? (odd ? 3 + (na - 3) / 2 : na / 2) : Nmax;
         s_st[3] += 1;
