@@ -61,7 +61,7 @@ __device__ __forceinline__ void scatter_pair_nr(double *vx, double *vy, double *
   if (um2 == KR(0)) return;
   const KR um = K::sqrt_(um2);
   const double wmax = wi > wj ? wi : wj;
-  const KR s = (KR)(coef_f_nmin_dV * wmax) / (um2 * um);
+  const KR s = K::div((KR)(coef_f_nmin_dV * wmax), um2 * um);
   if (!(s > KR(0))) return;
   const U4 r = philox(kp, cell, step_lo, c3, k0, k1);
   KR oc, st;

@@ -415,6 +415,7 @@ template <>
 struct KMath<double> {
   static __device__ __forceinline__ double u(uint32_t a) { return unif64(a); }
   static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+  static __device__ __forceinline__ double div(double a, double b) { return a / b; }
   static __device__ __forceinline__ double log_(double x) { return log(x); }
   static __device__ __forceinline__ double exp_(double x) { return exp(x); }
   static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
@@ -433,7 +434,11 @@ struct KMath<double> {
 template <>
 struct KMath<float> {
   static __device__ __forceinline__ float u(uint32_t a) { return unif32(a); }
-  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+  // FP32 kinematics: the hardware square root and reciprocal (about 1 ulp)
+  static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+  static __device__ __forceinline__ float div(float a, float b) {
+    return a * __builtin_amdgcn_rcpf(b);
+  }
   static __device__ __forceinline__ float log_(float x) {
     return __builtin_amdgcn_logf(x) * 0.69314718055994531f;
   }
@@ -591,7 +596,7 @@ __device__ __forceinline__ T n97_A_fast(T s, const double2 *tab) {
   if (!(s > T(0))) return T(__builtin_inf());
   if (s > M::S_ISO) return T(0);
   if (s >= T(N97_S_HI)) return T(3) * M::exp_(-s);
-  if (s <= T(N97_S_LO)) return T(1) / (-M::expm1_(-s));
+  if (s <= T(N97_S_LO)) return M::div(T(1), -M::expm1_(-s));
   const T x = (M::log_(s) - T(N97_T0)) * T(1.0 / N97_H);
   int i = (int)x;
   i = i < 0 ? 0 : (i > N97_TN - 2 ? N97_TN - 2 : i);
@@ -621,7 +626,7 @@ __device__ __forceinline__ void sample_angle(int method, T s, uint32_t a0, uint3
       oc = T(2);
       st = T(0);
     } else {
-      const T q = T(1) / (T(1) + d2);
+      const T q = M::div(T(1), T(1) + d2);
       st = T(2) * delta * q;
       oc = T(2) * d2 * q;
     }
@@ -632,7 +637,7 @@ __device__ __forceinline__ void sample_angle(int method, T s, uint32_t a0, uint3
     else if (A == T(0))
       oc = T(2) * u0;
     else
-      oc = -M::log1p_(u0 * M::expm1_(T(-2) * A)) / A;
+      oc = M::div(-M::log1p_(u0 * M::expm1_(T(-2) * A)), A);
     oc = oc < T(0) ? T(0) : (oc > T(2) ? T(2) : oc);
     st = M::sqrt_(oc * (T(2) - oc));
   }
@@ -647,7 +652,7 @@ __device__ __forceinline__ void rotate_delta(T ux, T uy, T uz, T st, T oc, T sp,
   const T up = M::sqrt_(up2);
   const T um = M::sqrt_(up2 + uz * uz);
   if (up > T(0)) {
-    const T ax = ux / up, ay = uy / up;
+    const T ax = M::div(ux, up), ay = M::div(uy, up);
     dx = ax * uz * st * cp - ay * um * st * sp - ux * oc;
     dy = ay * uz * st * cp + ax * um * st * sp - uy * oc;
     dz = -up * st * cp - uz * oc;
