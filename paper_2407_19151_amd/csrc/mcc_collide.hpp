@@ -533,6 +533,9 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   // compact layout (above, its room would cost a second resident cell per
   // CU); there a plan's order is read from HBM
   constexpr bool HAS_WORD = LAY != LAYOUT_COMPACT || CAP <= 1024;
+  // weights: in LDS except in the compact layout above 1024 particles, where
+  // their room would cost a resident cell per CU (read from HBM there)
+  constexpr bool W_LDS = LAY != LAYOUT_COMPACT || CAP <= 1024;
   static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
   static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT && !DIAG),
                 "the tangent form is FP64 non-relativistic, without diagnostics");
@@ -608,11 +611,15 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       M.kdot = lt + 6 * CAP;
     }
   } else if constexpr (LAY == LAYOUT_COMPACT) {
-    __shared__ double lv[3 * CAP];
+    __shared__ double lv[(W_LDS ? 4 : 3) * CAP];
     __shared__ __attribute__((aligned(16))) uint16_t lidx[(HAS_WORD ? 6 : 5) * CAP];
     M.vx = lv;
     M.vy = lv + CAP;
     M.vz = lv + 2 * CAP;
+    if constexpr (W_LDS) {
+      wdst = lv + 3 * CAP;
+      M.w = wdst;
+    }
     M.list0 = lidx;
     M.list1 = lidx + CAP;
     M.ord0 = lidx + 2 * CAP;
@@ -696,13 +703,13 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
     const int64_t cb = A.offsets[(int64_t)cell * S];
     const int n = uni(s_so[S]);
     const double dV = A.cell_volume ? A.cell_volume[cell] : A.dV;
-    if constexpr (LAY == LAYOUT_COMPACT) M.w = A.w + cb;
+    if constexpr (!W_LDS) M.w = A.w + cb;
 
     for (int e = t; e < n; e += TPC) {
       M.vx[e] = A.vx[cb + e];
       M.vy[e] = A.vy[cb + e];
       M.vz[e] = A.vz[cb + e];
-      if constexpr (LAY != LAYOUT_COMPACT) wdst[e] = A.w[cb + e];
+      if constexpr (W_LDS) wdst[e] = A.w[cb + e];
       if constexpr (TAN) {
         M.tx[e] = A.tx[cb + e];
         M.ty[e] = A.ty[cb + e];

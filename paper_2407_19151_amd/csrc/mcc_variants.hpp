@@ -86,7 +86,6 @@ inline constexpr Variant variant_of(int mode, int v) {
 constexpr int min_waves(int tpc, int cap, int layout, bool fp64, bool tangent) {
   if (tangent || layout == 2 || cap >= 2048) return 1;
   if (tpc == 64 && cap == 128) return 4;
-  if (tpc == 128 && cap == 512) return fp64 ? 3 : 4;
   return 3;
 }
 
