@@ -536,6 +536,9 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   // weights: in LDS except in the compact layout above 1024 particles, where
   // their room would cost a resident cell per CU (read from HBM there)
   constexpr bool W_LDS = LAY != LAYOUT_COMPACT || CAP <= 1024;
+  // pairs of intra-species collisions run as one pass (not in the tangent,
+  // relativistic and diagnostic forms)
+  constexpr bool DUAL = !TAN && !REL && !DIAG;
   static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
   static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT && !DIAG),
                 "the tangent form is FP64 non-relativistic, without diagnostics");
@@ -781,13 +784,32 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       }
     }
 
-    for (int k = 0; k < A.n_coll; ++k) {
+    for (int k = 0, kn = 0; k < A.n_coll; k = kn) {
+      kn = k + 1;
       const CollConst &C = s_coll[k];
-      const int a = uni(C.a), b = uni(C.b);
-      const bool intra = a == b;
+      const int a = uni(C.a);
+      const bool intra = a == uni(C.b);
       const int oa = uni(s_so[a]), na = uni(s_so[a + 1]) - oa;
+      if (intra && na < 2) continue;
+      // Two consecutive intra-species collisions of different species touch
+      // disjoint particles, so they commute and run as one pass ("dual"):
+      // each keeps its own random numbers, momentum restore, energy
+      // correction and failure decision; species b is then the second one's.
+      bool dual = false;
+      int b = uni(C.b);
+      if constexpr (DUAL) {
+        if (intra && k + 1 < A.n_coll) {
+          const int a2 = uni(s_coll[k + 1].a);
+          if (a2 == uni(s_coll[k + 1].b) && a2 != a && uni(s_so[a2 + 1]) - uni(s_so[a2]) >= 2) {
+            dual = true;
+            b = a2;
+            kn = k + 2;
+          }
+        }
+      }
       const int ob = uni(s_so[b]), nb = uni(s_so[b + 1]) - ob;
-      if (intra ? (na < 2) : (na == 0 || nb == 0)) continue;
+      if (!intra && (na == 0 || nb == 0)) continue;
+      const bool two = !intra || dual;  // a second species takes part
       const double ma = uni(s_mass[a]), mb = uni(s_mass[b]);
 
       MCC_PHASE(1);  // snapshot and shuffles
@@ -818,15 +840,16 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       // random binary pairs (Fig. 1)
       // L0, L1: the shuffled lists of species a and b
       const uint16_t *L0 = M.list0, *L1 = M.list0 + na;
-      if (intra)
+      if (!two)
         shuffle_species<TPC, PPT, GL>(M, na, oa, (uint32_t)cell, step_lo,
                                       ctr3(step, k, PURPOSE_SHUFFLE0 + 0), k0, k1, M.list0,
                                       wsum, &maxocc);
       else
         shuffle_two<TPC, PPT, GL>(M, na, oa, nb, ob, (uint32_t)cell, step_lo,
                                   ctr3(step, k, PURPOSE_SHUFFLE0 + 0),
-                                  ctr3(step, k, PURPOSE_SHUFFLE0 + 1), k0, k1, M.list0, wsum,
-                                  &maxocc);
+                                  dual ? ctr3(step, k + 1, PURPOSE_SHUFFLE0 + 0)
+                                       : ctr3(step, k, PURPOSE_SHUFFLE0 + 1),
+                                  k0, k1, M.list0, wsum, &maxocc);
 
       // scatter (Sec. 3.2 pairing) in rounds of disjoint pairs:
       //  intra, even N: one round (L0,L1),(L2,L3),...
@@ -843,17 +866,28 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       // the odd triple (L0,L1),(L1,L2),(L2,L0); in an inter-species collision
       // the pairs k, k + N_min, k + 2 N_min, ... (they share small[k]).
       // Different chains touch disjoint particles, so one barrier ends the
-      // scatter and every particle sees its pairs in ascending k.
-      const int nchains = intra ? (odd ? 1 + (na - 3) / 2 : na / 2) : Nmin;
-      for (int ch = t; ch < nchains; ch += TPC) {
-        const int len = intra ? ((odd && ch == 0) ? 3 : 1) : (Nmax - ch + Nmin - 1) / Nmin;
+      // scatter and every particle sees its pairs in ascending k.  A dual
+      // pass runs the chains of species b after those of species a.
+      const int ncha = intra ? (odd ? 1 + (na - 3) / 2 : na / 2) : Nmin;
+      const bool oddb = dual && (nb & 1);
+      const int nchb = dual ? (oddb ? 1 + (nb - 3) / 2 : nb / 2) : 0;
+      const uint32_t c3pb = ctr3(step, k + 1, PURPOSE_PAIR);
+      for (int ch0 = t; ch0 < ncha + nchb; ch0 += TPC) {
+        const bool sb = ch0 >= ncha;  // (dual pass) a chain of species b
+        const int ch = sb ? ch0 - ncha : ch0;
+        const bool odds = sb ? oddb : odd;
+        const int len = intra ? ((odds && ch == 0) ? 3 : 1) : (Nmax - ch + Nmin - 1) / Nmin;
+        // the constants of the collision this chain belongs to
+        const CollConst &Cs = s_coll[sb ? k + 1 : k];
+        const double nmins = sb ? (double)(nb - 1) : nmin;
+        const uint32_t c3s = sb ? c3pb : c3p;
         for (int r = 0; r < len; ++r) {
           int I, J;
           uint32_t kp;
           double f = 1.0;
           if (intra) {
-            const uint16_t *L = L0;
-            if (odd) {
+            const uint16_t *L = sb ? L1 : L0;
+            if (odds) {
               if (ch == 0) {
                 I = L[r];
                 J = L[r == 2 ? 0 : r + 1];
@@ -876,7 +910,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             J = abig ? L1[ch] : L1[kk];
             kp = (uint32_t)kk;
           }
-          const double cf = C.coef * f * (nmin / dV);
+          const double cf = Cs.coef * f * (nmins / dV);
           if constexpr (REL)
             scatter_pair_rel(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, ma, mb, A.c, A.method,
                              (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
@@ -884,56 +918,77 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             scatter_pair_nr_tan(M.vx, M.vy, M.vz, M.tx, M.ty, M.tz, M.w, I, J, kp, cf, C.fa, C.fb,
                                 A.method, (uint32_t)cell, step_lo, c3p, k0, k1, A.n97, A.dlnl);
           else if constexpr (sizeof(KR) == 8)
-            scatter_pair_nr_f64(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, C.fa, C.fb, A.method,
-                                (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
+            scatter_pair_nr_f64(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, Cs.fa, Cs.fb, A.method,
+                                (uint32_t)cell, step_lo, c3s, k0, k1, A.n97);
           else
-            scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, C.fa, C.fb, A.method,
-                                (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
+            scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, Cs.fa, Cs.fb, A.method,
+                                (uint32_t)cell, step_lo, c3s, k0, k1, A.n97);
         }
       }
       __syncthreads();
       if (t == 0) {
         s_st[0] += intra ? (odd ? 3 + (na - 3) / 2 : na / 2) : Nmax;
-        s_st[3] += 1;
+        if (dual) s_st[0] += oddb ? 3 + (nb - 3) / 2 : nb / 2;
+        s_st[3] += dual ? 2 : 1;
       }
 
       MCC_PHASE(3);  // momentum restore and energy sums
       if (!A.corr) continue;
 
       auto part = [&](int e) {
-        return (e >= oa && e < oa + na) || (!intra && e >= ob && e < ob + nb);
+        return (e >= oa && e < oa + na) || (two && e >= ob && e < ob + nb);
       };
       auto mass_of = [&](int e) { return (e >= oa && e < oa + na) ? ma : mb; };
 
       // momentum restore, Eq. (17): B = sum m_p (v_ps - v_bs) / sum m_p w_p;
       // v -= B w is applied in the energy pass below
       double Bx, By, Bz;
+      double Bbx = 0.0, Bby = 0.0, Bbz = 0.0;  // species b of a dual pass
       {
         constexpr int NP = TAN ? 6 : 3;  // the tangent of the sums rides along
-        double P[NP];
+        // P[3..5]: the tangent sums, or species b's sums of a dual pass
+        double P[6];
 #pragma unroll
-        for (int i = 0; i < NP; ++i) P[i] = 0.0;
+        for (int i = 0; i < 6; ++i) P[i] = 0.0;
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
           if (e < n && part(e)) {
             const double mp = mass_of(e) * M.w[e];
-            P[0] += mp * (M.vx[e] - SNAPX(j, e));
-            P[1] += mp * (M.vy[e] - SNAPY(j, e));
-            P[2] += mp * (M.vz[e] - SNAPZ(j, e));
+            const double dx = mp * (M.vx[e] - SNAPX(j, e));
+            const double dy = mp * (M.vy[e] - SNAPY(j, e));
+            const double dz = mp * (M.vz[e] - SNAPZ(j, e));
+            if (dual && !(e >= oa && e < oa + na)) {
+              P[3] += dx;
+              P[4] += dy;
+              P[5] += dz;
+            } else {
+              P[0] += dx;
+              P[1] += dy;
+              P[2] += dz;
+            }
             if constexpr (TAN) {
-              P[3 % NP] += mp * (M.tx[e] - M.btx[e]);
-              P[4 % NP] += mp * (M.ty[e] - M.bty[e]);
-              P[5 % NP] += mp * (M.tz[e] - M.btz[e]);
+              P[3] += mp * (M.tx[e] - M.btx[e]);
+              P[4] += mp * (M.ty[e] - M.bty[e]);
+              P[5] += mp * (M.tz[e] - M.btz[e]);
             }
           }
         });
-        double tot[NP];
-        block_sum<TPC, NP>(P, red, tot);
+        double tot[6];
+        if (dual)
+          block_sum<TPC, 6>(P, red, tot);
+        else
+          block_sum<TPC, NP>(P, red, tot);
         const double D = ma * s_sw2[a] + (intra ? 0.0 : mb * s_sw2[b]);
         Bx = tot[0] / D;
         By = tot[1] / D;
         Bz = tot[2] / D;
+        if (dual) {
+          const double Db = mb * s_sw2[b];
+          Bbx = tot[3] / Db;
+          Bby = tot[4] / Db;
+          Bbz = tot[5] / Db;
+        }
         if constexpr (TAN) {
-          const double tBx = tot[3 % NP] / D, tBy = tot[4 % NP] / D, tBz = tot[5 % NP] / D;
+          const double tBx = tot[3] / D, tBy = tot[4] / D, tBz = tot[5] / D;
           for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
             if (e < n && part(e)) {
               const double we = M.w[e];
@@ -953,6 +1008,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         // decides how many pairs the correction uses) and, for an
         // inter-species collision, the kinetic energy of each species
         double es = 0.0, ec = 0.0;
+        double es1 = 0.0, ec1 = 0.0;  // species b of a dual pass
         // KE_a, KE_b; tangent form: then the tangents of dE, KE_a, KE_b
         constexpr int NE = TAN ? 5 : 2;
         double Ev[NE];
@@ -962,9 +1018,12 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
           if (e < n && part(e)) {
             const bool isa = e >= oa && e < oa + na;
+            const bool sb = dual && !isa;
             const double we = M.w[e];
             const double mp = (isa ? ma : mb) * we;
-            const double vx = M.vx[e] - Bx * we, vy = M.vy[e] - By * we, vz = M.vz[e] - Bz * we;
+            const double rbx = sb ? Bbx : Bx, rby = sb ? Bby : By, rbz = sb ? Bbz : Bz;
+            const double vx = M.vx[e] - rbx * we, vy = M.vy[e] - rby * we,
+                         vz = M.vz[e] - rbz * we;
             M.vx[e] = vx;
             M.vy[e] = vy;
             M.vz[e] = vz;
@@ -981,7 +1040,10 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
               term = 0.5 * mp * dd;
               ke = 0.5 * mp * (vx * vx + vy * vy + vz * vz);
             }
-            csum_add(es, ec, term);
+            if (sb)
+              csum_add(es1, ec1, term);
+            else
+              csum_add(es, ec, term);
             if (isa)
               Ev[0] += ke;
             else
@@ -1014,6 +1076,9 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             tdEs0 = tr * dE + ra * tdE;
             tdEs1 = -tr * dE + rb * tdE;
           }
+        } else if (dual) {
+          // two intra-species violations, each corrected on its own species
+          block_sum_c2<TPC>(es, ec, es1, ec1, red, dEs0, dEs1);
         } else if (intra) {
           double tot[1];
           block_sum_c1<TPC, 1>(es, ec, Ev, red, dEs0, tot);
@@ -1030,7 +1095,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       }
 
       // correction order per species (Alg. 1, optional sort), then the pair loop
-      const int nsl = intra ? 1 : 2;
+      const int nsl = two ? 2 : 1;
       const uint16_t *O0 = L0, *O1 = L1;
       if (A.sortw) {
         auto order = [&](int sp, int o, int ns, const uint16_t *L, uint16_t *ord) {
@@ -1048,7 +1113,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
           return (const uint16_t *)ord;
         };
         O0 = order(a, oa, na, L0, M.ord0);
-        if (!intra) O1 = order(b, ob, nb, L1, M.ord1);
+        if (two) O1 = order(b, ob, nb, L1, M.ord1);
       }
       double *Kb = M.kbuf;
       const int base1 = na / 2;           // pair slots of the second species
@@ -1266,14 +1331,17 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         __syncthreads();
       }
       MCC_PHASE(8);  // failure handling and diagnostics
-      const bool failed = resid0 != 0.0 || resid1 != 0.0;
+      // one decision per collision: for both species of an inter-species
+      // collision, per species in a dual pass
+      const bool failA = dual ? resid0 != 0.0 : (resid0 != 0.0 || resid1 != 0.0);
+      const bool failB = dual ? resid1 != 0.0 : failA;
       if (t == 0) {
         s_st[1] += used_total;
-        s_st[2] += failed ? 1 : 0;
+        s_st[2] += (failA ? 1 : 0) + (dual && failB ? 1 : 0);
       }
-      if (failed && !A.keep) {  // Sec. 6.2: reset this collision in this cell
+      if ((failA || failB) && !A.keep) {  // Sec. 6.2: reset this collision in this cell
         for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
-                    if (e < n && part(e)) {
+          if (e < n && part(e) && ((e >= oa && e < oa + na) ? failA : failB)) {
             M.vx[e] = SNAPX(j, e);
             M.vy[e] = SNAPY(j, e);
             M.vz[e] = SNAPZ(j, e);

@@ -224,6 +224,56 @@ __device__ __forceinline__ void block_sum_c1(double &s, double &c, double v[N], 
   __syncthreads();
 }
 
+// Two compensated values summed over the block in one pass, each exactly as
+// block_sum_c1 sums its one (same butterfly, same order across waves);
+// every thread receives both totals.  `red` holds at least 4*(TPC/64)
+// doubles.  Ends with a barrier.
+template <int TPC>
+__device__ __forceinline__ void block_sum_c2(double &s0, double &c0, double &s1, double &c1,
+                                             double *red, double &out0, double &out1) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  constexpr int NW = TPC / WAVE;
+#pragma unroll
+  for (int off = WAVE / 2; off > 0; off >>= 1) {
+    const double a2 = __shfl_xor(s0, off), ac = __shfl_xor(c0, off);
+    const double b2 = __shfl_xor(s1, off), bc = __shfl_xor(c1, off);
+    double t, e;
+    two_sum(s0, a2, t, e);
+    s0 = t;
+    c0 = c0 + ac + e;
+    two_sum(s1, b2, t, e);
+    s1 = t;
+    c1 = c1 + bc + e;
+  }
+  if (NW == 1) {
+    out0 = s0 + c0;
+    out1 = s1 + c1;
+    __syncthreads();
+    return;
+  }
+  if (lane == 0) {
+    red[wid * 4] = s0;
+    red[wid * 4 + 1] = c0;
+    red[wid * 4 + 2] = s1;
+    red[wid * 4 + 3] = c1;
+  }
+  __syncthreads();
+  double ss0 = red[0], cc0 = red[1], ss1 = red[2], cc1 = red[3];
+  for (int w = 1; w < NW; ++w) {
+    double t, e;
+    two_sum(ss0, red[w * 4], t, e);
+    ss0 = t;
+    cc0 = cc0 + red[w * 4 + 1] + e;
+    two_sum(ss1, red[w * 4 + 2], t, e);
+    ss1 = t;
+    cc1 = cc1 + red[w * 4 + 3] + e;
+  }
+  out0 = ss0 + cc0;
+  out1 = ss1 + cc1;
+  __syncthreads();
+}
+
 // min and max of N u64 values over the block (all threads receive them)
 template <int TPC, int N, bool G = false>
 __device__ __forceinline__ void block_minmax_u64(uint64_t lo[N], uint64_t hi[N], uint64_t *red) {

@@ -119,6 +119,22 @@ def test_parity_three_species_and_collision_order(ctx):
     _parity(ctx, wl, 4)
 
 
+def test_parity_consecutive_intra_collisions(ctx):
+    """Back-to-back intra-species collisions of different species touch
+    disjoint particles; the kernel runs such a pair as one pass.  Each keeps
+    its own counters, restore, correction and failure decision, so the
+    result is the oracle's sequential one.  Covered: chains of such pairs,
+    a repeated species (never merged), species with fewer than two
+    particles, odd counts, and forced failures with both failure policies."""
+    sizes = [(40, 30, 21), (1, 50, 33), (0, 2, 7), (3, 3, 3), (1501, 1000, 600), (2, 1, 0)]
+    coll = ((0, 0), (1, 1), (2, 2), (0, 0), (0, 0), (1, 0), (2, 2), (1, 1))
+    wl = custom_workload(sizes, seed=11, masses=(1.0, 4.0, 50.0), charges=(-1.0, 2.0, 3.0),
+                         collisions=coll)
+    _parity(ctx, wl.copy(), 2)
+    _parity(ctx, wl.copy(), 3, f_E=0.01, max_passes=1)
+    _parity(ctx, wl.copy(), 3, f_E=0.01, max_passes=1, on_failure=1)
+
+
 def test_parity_relativistic_subset(ctx):
     wl = W.config4(n_cells=8)
     _parity(ctx, wl, 0)
