@@ -106,6 +106,10 @@ struct mcc_ctx {
   int32_t *err = nullptr;  // device error word
   DevBuf lists, counts, big4k, big32k;
   DevBuf n97;  // N97 A(s) table (built once)
+  // per size bucket: the collide kernels' cell-claim and finished-workgroup
+  // counters (zero between launches: each launch resets them at its end, so
+  // launches of one context must not overlap)
+  DevBuf work;
   // unsorted entry
   DevBuf ucnt, tiles, off, cursor, perm, biglist, bigcount, canon, gw, gx, gy, gz;
   int grid[NMODE][NVARIANT] = {};
@@ -272,6 +276,7 @@ mcc_status launch_bucket(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_
 #endif
   A.cell_list = lists + (int64_t)b * std::max(n_cells, 1);
   A.cell_count = counts + b;
+  A.work = ctx->work.as<uint32_t>() + WORK_QUEUES * WORK_STRIDE * b;
   set_big_args(ctx, A, mode, v);
   void *kargs[] = {&A};
   HIP_TRY(hipLaunchKernel(tab[v], dim3(grid_of(ctx, mode, v)), dim3(variant_of(mode, v).tpc),
@@ -369,6 +374,12 @@ mcc_status mcc_create(mcc_ctx **out, int device, void *hip_stream) {
   if (e == hipSuccess)
     e = ctx->n97.ensure(sizeof(double2) * N97_TABLE_SIZE) ? hipSuccess : hipErrorOutOfMemory;
   if (e == hipSuccess) e = launch_n97_table(ctx->n97.as<double2>(), nullptr);
+  if (e == hipSuccess)
+    e = ctx->work.ensure(sizeof(uint32_t) * WORK_QUEUES * WORK_STRIDE * NBUCKET)
+            ? hipSuccess
+            : hipErrorOutOfMemory;
+  if (e == hipSuccess)
+    e = hipMemset(ctx->work.p, 0, sizeof(uint32_t) * WORK_QUEUES * WORK_STRIDE * NBUCKET);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     delete ctx;
@@ -403,7 +414,8 @@ void mcc_destroy(mcc_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->big4k, &ctx->big32k, &ctx->ucnt, &ctx->tiles,
                     &ctx->off, &ctx->cursor, &ctx->perm, &ctx->biglist, &ctx->bigcount,
-                    &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97})
+                    &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97,
+                    &ctx->work})
     b->release();
   if (ctx->err) (void)hipFree(ctx->err);
   delete ctx;
@@ -670,6 +682,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
         CollideArgs A = T;
         A.cell_list = pl->lists.as<int32_t>() + (int64_t)b * std::max(n_cells, 1);
         A.cell_count = pl->counts.as<uint32_t>() + b;
+        A.work = ctx->work.as<uint32_t>() + WORK_QUEUES * WORK_STRIDE * b;
         set_big_args(ctx, A, pl->mode, v);
         void *kargs[] = {&A};
         float ms_best = 1e30f;
@@ -715,7 +728,8 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
   // step
   if (p->moment_correction && n_cells > 0) {
     if (!pl->prep.ensure(sizeof(SpeciesPrep) * (size_t)n_cells * n_species) ||
-        !pl->prep_word.ensure(sizeof(uint16_t) * (size_t)std::max<int64_t>(n, 1))) {
+        // (+4: the kernel reads a cell's entries in whole dwords)
+        !pl->prep_word.ensure(sizeof(uint16_t) * (size_t)(std::max<int64_t>(n, 1) + 4))) {
       mcc_plan_destroy(pl);
       return MCC_ERR_OOM;
     }
@@ -789,8 +803,9 @@ mcc_status mcc_plan_describe(mcc_plan *pl, char *buf, size_t len) {
     char tmp[512];
     std::snprintf(tmp, sizeof(tmp),
                   "%s{\"max_cell\": %d, \"cells\": %u, \"tpc\": %d, \"cap\": %d, \"layout\": %d, "
-                  "\"timed_ms\": {",
-                  b ? ", " : "", kBucketCap[b], hc[b], V.tpc, V.cap, V.layout);
+                  "\"grid\": %d, \"timed_ms\": {",
+                  b ? ", " : "", kBucketCap[b], hc[b], V.tpc, V.cap, V.layout,
+                  grid_of(pl->ctx, pl->mode, pl->variant[b]));
     out += tmp;
     bool first = true;
     for (int u = 0; u < NVARIANT; ++u) {

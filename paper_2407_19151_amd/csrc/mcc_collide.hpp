@@ -548,8 +548,11 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   __shared__ uint32_t maxocc;
   __shared__ int s_so[MCC_MAX_SPECIES + 1];
   __shared__ int s_bad;
+  __shared__ long long s_cb;  // first particle of the cell
+  __shared__ uint32_t s_next[2];  // the next work-list entry (double-buffered)
+  // per species: sum w, sum w^2, the weight range (bit patterns) and class
   __shared__ unsigned long long s_wlo[MCC_MAX_SPECIES], s_whi[MCC_MAX_SPECIES];
-  __shared__ double s_sw[MCC_MAX_SPECIES], s_sw2[MCC_MAX_SPECIES];  // sum w, sum w^2
+  __shared__ double s_sw[MCC_MAX_SPECIES], s_sw2[MCC_MAX_SPECIES];
   __shared__ int s_wflag[MCC_MAX_SPECIES];
   __shared__ unsigned long long s_st[4];  // pairs, correction pairs, failures, collisions
   __shared__ double s_sd[2];              // diagnostics maxima
@@ -557,8 +560,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   __shared__ double s_res[2];
   __shared__ double s_tres[2];  // tangent form: tangent of the residuals
   __shared__ int s_used[2];
-  __shared__ double s_mass[MCC_MAX_SPECIES];
-  __shared__ CollConst s_coll[MCC_MAX_COLLISIONS];
+  __shared__ CollConst s_cc[2];  // the collision(s) of the current pass
   // bucket counters stay in LDS in every layout: global atomics complete in
   // L2, and later plain loads could hit stale L1 lines
   __shared__ __attribute__((aligned(16))) uint32_t lcnt[CAP + 2];
@@ -589,7 +591,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   if constexpr (LAY == LAYOUT_LDS) {
     __shared__ double lv[4 * CAP];
     __shared__ uint64_t lscr[CAP + 1];
-    __shared__ uint16_t lidx[6 * CAP];
+    __shared__ __attribute__((aligned(16))) uint16_t lidx[6 * CAP + 4];
     M.vx = lv;
     M.vy = lv + CAP;
     M.vz = lv + 2 * CAP;
@@ -615,7 +617,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
     }
   } else if constexpr (LAY == LAYOUT_COMPACT) {
     __shared__ double lv[(W_LDS ? 4 : 3) * CAP];
-    __shared__ __attribute__((aligned(16))) uint16_t lidx[(HAS_WORD ? 6 : 5) * CAP];
+    __shared__ __attribute__((aligned(16))) uint16_t lidx[(HAS_WORD ? 6 : 5) * CAP + 4];
     M.vx = lv;
     M.vy = lv + CAP;
     M.vz = lv + 2 * CAP;
@@ -666,75 +668,131 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
     }
   }
 
+  uint16_t *const wbase = M.word;  // LDS home of the descending-weight order
   const int t = threadIdx.x;
   const int S = A.S;
   const uint64_t step = A.step_dev ? *A.step_dev : A.step;
   const uint32_t step_lo = (uint32_t)step;
   const uint32_t k0 = (uint32_t)A.seed, k1 = (uint32_t)(A.seed >> 32);
   const uint32_t count = *A.cell_count;
+  // Cells are handed out at run time, so no workgroup idles while another
+  // still holds several.  The work list is split into NQ interleaved queues
+  // (queue q: entries q, q + NQ, q + 2 NQ, ...) whose counters sit in
+  // separate 256-byte lines, so claims on different queues do not serialize;
+  // the first entries of a queue go to its workgroups in order, the rest are
+  // claimed one at a time (qctr[0]).  qctr[1] counts the workgroups of the
+  // queue that ran out; the last one resets both for the next launch.
+  const uint32_t NQ = gridDim.x < WORK_QUEUES ? gridDim.x : WORK_QUEUES;
+  const uint32_t q = blockIdx.x % NQ;
+  const uint32_t nq = (gridDim.x - q + NQ - 1) / NQ;  // workgroups on queue q
+  uint32_t *const qctr = A.work + q * WORK_STRIDE;
+  int par = 0;
   // per-species and per-collision constants in LDS (indexed at run time)
-  if (t < MCC_MAX_SPECIES) s_mass[t] = A.mass[t];
-  if (t < MCC_MAX_COLLISIONS) s_coll[t] = A.coll[t];
-  __syncthreads();
 
-  for (uint32_t li = blockIdx.x; li < count; li += gridDim.x) {
+  for (uint32_t li = q + NQ * (blockIdx.x / NQ); li < count;) {
     MCC_PHASE(0);  // header and staging
     const int cell = A.cell_list[li];
-    // cell header: segment offsets, validated once
-    if (t == 0) {
-      const int64_t cb = A.offsets[(int64_t)cell * S];
-      const int64_t ce = A.offsets[(int64_t)(cell + 1) * S];
-      int bad = (cb >= 0 && ce >= cb && ce <= A.n) ? 0 : 1;
-      for (int s = 0; s < S; ++s) {
-        const int64_t o = A.offsets[(int64_t)cell * S + s];
-        const int64_t o1 = A.offsets[(int64_t)cell * S + s + 1];
-        if (o < cb || o1 < o || o1 > ce) bad = 1;
-        s_so[s] = (int)(o - cb);
-      }
-      s_so[S] = (int)(ce - cb);
+    // the next entry, claimed now and needed only when this cell is done
+    uint32_t claim = 0;
+    if (t == 0) claim = atomicAdd(qctr, 1u);
+    // cell header: the S + 1 segment offsets, one per lane of wave 0 (one
+    // load latency), validated once
+    if (t < WAVE) {
+      const int64_t o = t <= S ? A.offsets[(int64_t)cell * S + t] : 0;
+      const int64_t cb = __shfl(o, 0), ce = __shfl(o, S);
+      const int64_t o1 = __shfl_down(o, 1);
+      int bad = (t == 0 && !(cb >= 0 && ce >= cb && ce <= A.n)) ||
+                (t < S && (o < cb || o1 < o || o1 > ce));
+      bad = __ballot(bad) ? 1 : 0;
       if (!bad && ce - cb > CAP) bad = 2;
-      if (bad) atomicCAS(A.err, 0, bad);
-      s_bad = bad;
-      for (int q = 0; q < 4; ++q) s_st[q] = 0ull;
-      s_sd[0] = s_sd[1] = 0.0;
+      if (t <= S) s_so[t] = (int)(o - cb);
+      if (t == 0) {
+        if (bad) atomicCAS(A.err, 0, bad);
+        s_bad = bad;
+        s_cb = cb;
+        for (int q = 0; q < 4; ++q) s_st[q] = 0ull;
+        s_sd[0] = s_sd[1] = 0.0;
+      }
     }
     __syncthreads();
     if (s_bad) {
+      if (t == 0) s_next[par] = q + NQ * (nq + claim);
       __syncthreads();
+      li = uni((int)s_next[par]);  // (the next write goes to the other slot)
+      par ^= 1;
       continue;  // uniform over the workgroup
     }
-    const int64_t cb = A.offsets[(int64_t)cell * S];
+    const int64_t cb = uni(s_cb);
     const int n = uni(s_so[S]);
     const double dV = A.cell_volume ? A.cell_volume[cell] : A.dV;
     if constexpr (!W_LDS) M.w = A.w + cb;
+    const bool prep_read = A.corr && A.prep_mode == PREP_READ;
 
-    for (int e = t; e < n; e += TPC) {
-      M.vx[e] = A.vx[cb + e];
-      M.vy[e] = A.vy[cb + e];
-      M.vz[e] = A.vz[cb + e];
-      if constexpr (W_LDS) wdst[e] = A.w[cb + e];
+    if constexpr (!GL) {
+      // straight from HBM into LDS (no registers), every copy of the cell in
+      // flight at once: the cell costs one HBM latency
+      lds_copy<TPC>(A.vx + cb, M.vx, 2 * n);
+      lds_copy<TPC>(A.vy + cb, M.vy, 2 * n);
+      lds_copy<TPC>(A.vz + cb, M.vz, 2 * n);
+      if constexpr (W_LDS) lds_copy<TPC>(A.w + cb, wdst, 2 * n);
       if constexpr (TAN) {
-        M.tx[e] = A.tx[cb + e];
-        M.ty[e] = A.ty[cb + e];
-        M.tz[e] = A.tz[cb + e];
+        lds_copy<TPC>(A.tx + cb, M.tx, 2 * n);
+        lds_copy<TPC>(A.ty + cb, M.ty, 2 * n);
+        lds_copy<TPC>(A.tz + cb, M.tz, 2 * n);
       }
-    }
-    __syncthreads();
-    if (A.corr && A.prep_mode == PREP_READ) {
-      // the plan's weight data of this cell
-      if (t < S) {
-        const SpeciesPrep P = A.prep[(int64_t)cell * S + t];
+      SpeciesPrep P{};
+      if (prep_read && t < S) P = A.prep[(int64_t)cell * S + t];
+      if (prep_read) {
+        // the plan's weight data of this cell; its u16 word order is copied
+        // in whole dwords from the even entry at or below cb, so the cell's
+        // first entry lands at (cb & 1)
+        if constexpr (HAS_WORD) {
+          const int odd0 = (int)(cb & 1);
+          lds_copy<TPC>(A.prep_word + (cb - odd0), wbase, (n + odd0 + 1) >> 1);
+          M.word = wbase + odd0;
+        }
+      } else if constexpr (HAS_WORD) {
+        M.word = wbase;
+      }
+      lds_copy_wait();
+      if (prep_read && t < S) {
         s_sw[t] = P.sw;
         s_sw2[t] = P.sw2;
         s_wlo[t] = P.lo;
         s_whi[t] = P.hi;
         s_wflag[t] = P.flag;
       }
-      if constexpr (HAS_WORD) {
-        for (int e = t; e < n; e += TPC) M.word[e] = A.prep_word[cb + e];
+      __syncthreads();
+    } else {
+      for (int e = t; e < n; e += TPC) {
+        M.vx[e] = A.vx[cb + e];
+        M.vy[e] = A.vy[cb + e];
+        M.vz[e] = A.vz[cb + e];
+        if constexpr (W_LDS) wdst[e] = A.w[cb + e];
+        if constexpr (TAN) {
+          M.tx[e] = A.tx[cb + e];
+          M.ty[e] = A.ty[cb + e];
+          M.tz[e] = A.tz[cb + e];
+        }
       }
       __syncthreads();
-    } else if (A.corr) {
+      if (prep_read) {
+        // the plan's weight data of this cell
+        if (t < S) {
+          const SpeciesPrep P = A.prep[(int64_t)cell * S + t];
+          s_sw[t] = P.sw;
+          s_sw2[t] = P.sw2;
+          s_wlo[t] = P.lo;
+          s_whi[t] = P.hi;
+          s_wflag[t] = P.flag;
+        }
+        if constexpr (HAS_WORD) {
+          for (int e = t; e < n; e += TPC) M.word[e] = A.prep_word[cb + e];
+        }
+        __syncthreads();
+      }
+    }
+    if (!prep_read && A.corr) {
       // per species, once per cell: sum w and sum w^2 (the denominator of
       // Eq. (17) and the mean weights of Eq. (24)), the weight range, and
       // for unequal weights the descending-weight order, which is the
@@ -786,9 +844,8 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
 
     for (int k = 0, kn = 0; k < A.n_coll; k = kn) {
       kn = k + 1;
-      const CollConst &C = s_coll[k];
-      const int a = uni(C.a);
-      const bool intra = a == uni(C.b);
+      const int a = uni(A.coll[k].a);
+      const bool intra = a == uni(A.coll[k].b);
       const int oa = uni(s_so[a]), na = uni(s_so[a + 1]) - oa;
       if (intra && na < 2) continue;
       // Two consecutive intra-species collisions of different species touch
@@ -796,11 +853,11 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       // each keeps its own random numbers, momentum restore, energy
       // correction and failure decision; species b is then the second one's.
       bool dual = false;
-      int b = uni(C.b);
+      int b = uni(A.coll[k].b);
       if constexpr (DUAL) {
         if (intra && k + 1 < A.n_coll) {
-          const int a2 = uni(s_coll[k + 1].a);
-          if (a2 == uni(s_coll[k + 1].b) && a2 != a && uni(s_so[a2 + 1]) - uni(s_so[a2]) >= 2) {
+          const int a2 = uni(A.coll[k + 1].a);
+          if (a2 == uni(A.coll[k + 1].b) && a2 != a && uni(s_so[a2 + 1]) - uni(s_so[a2]) >= 2) {
             dual = true;
             b = a2;
             kn = k + 2;
@@ -810,7 +867,14 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       const int ob = uni(s_so[b]), nb = uni(s_so[b + 1]) - ob;
       if (!intra && (na == 0 || nb == 0)) continue;
       const bool two = !intra || dual;  // a second species takes part
-      const double ma = uni(s_mass[a]), mb = uni(s_mass[b]);
+      const double ma = A.mass[a], mb = A.mass[b];
+      // the constants the scatter reads (written before the shuffles' barriers;
+      // the previous pass read them before its scatter barrier)
+      if (t == 0) {
+        s_cc[0] = A.coll[k];
+        if (dual) s_cc[1] = A.coll[k + 1];
+      }
+      const CollConst &C = s_cc[0];
 
       MCC_PHASE(1);  // snapshot and shuffles
       // pre-scatter snapshot (Alg. 1, first step)
@@ -878,7 +942,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         const bool odds = sb ? oddb : odd;
         const int len = intra ? ((odds && ch == 0) ? 3 : 1) : (Nmax - ch + Nmin - 1) / Nmin;
         // the constants of the collision this chain belongs to
-        const CollConst &Cs = s_coll[sb ? k + 1 : k];
+        const CollConst &Cs = s_cc[sb ? 1 : 0];
         const double nmins = sb ? (double)(nb - 1) : nmin;
         const uint32_t c3s = sb ? c3pb : c3p;
         for (int r = 0; r < len; ++r) {
@@ -1202,25 +1266,13 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             for (int m0 = 0; m0 < np && absE != 0.0; m0 += WAVE) {
               const int m = m0 + lane;
               const double lim = m < np ? A.fE * Kb[kb + m] : 0.0;
-              double P = lim;
-#pragma unroll
-              for (int d = 1; d < WAVE; d <<= 1) {
-                const double y = __shfl_up(P, d);
-                if (lane >= d) P += y;
-              }
-              double Pprev = __shfl_up(P, 1);
-              if (lane == 0) Pprev = 0.0;
+              const double P = wave_incl_scan(lim);
+              const double Pprev = wave_shr1(P);  // (0 in lane 0)
               double tlim = 0.0, tP = 0.0, tPprev = 0.0;
               if constexpr (TAN) {
                 tlim = m < np ? A.fE * M.kdot[kb + m] : 0.0;
-                tP = tlim;
-#pragma unroll
-                for (int d = 1; d < WAVE; d <<= 1) {
-                  const double y = __shfl_up(tP, d);
-                  if (lane >= d) tP += y;
-                }
-                tPprev = __shfl_up(tP, 1);
-                if (lane == 0) tPprev = 0.0;
+                tP = wave_incl_scan(tlim);
+                tPprev = wave_shr1(tP);
               }
               const unsigned long long hit = __ballot(m < np && P >= absE);
               if (hit) {
@@ -1241,8 +1293,8 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
                 }
                 used += __popcll(__ballot(m < np && lim != 0.0));
                 const int last = (np - m0 < WAVE ? np - m0 : WAVE) - 1;
-                absE -= __shfl(P, last);
-                if constexpr (TAN) tabsE -= __shfl(tP, last);
+                absE -= wave_bcast(P, last);
+                if constexpr (TAN) tabsE -= wave_bcast(tP, last);
                 ncut = m0 + last + 1;
               }
             }
@@ -1424,7 +1476,18 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         }
       }
     }
+    if (t == 0) s_next[par] = q + NQ * (nq + claim);
     __syncthreads();
+    li = uni((int)s_next[par]);  // (the next write goes to the other slot)
+    par ^= 1;
+  }
+  if (t == 0) {
+    // every claim of this workgroup has returned; the last one of its queue
+    // resets the queue's counters (all other claims are complete by then)
+    if (atomicAdd(qctr + 1, 1u) == nq - 1) {
+      atomicExch(qctr, 0u);
+      atomicExch(qctr + 1, 0u);
+    }
   }
 #ifdef MCC_PHASE_TIMING
   MCC_PHASE(15);

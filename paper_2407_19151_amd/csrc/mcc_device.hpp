@@ -49,8 +49,32 @@ __device__ __forceinline__ uint32_t ctr3(uint64_t step, int coll, uint32_t purpo
   return (uint32_t)(((step >> 32) & 0xFFFFu) << 16) | ((uint32_t)(coll & 0xFF) << 8) | purpose;
 }
 
+// Copies ndw dwords from global memory into LDS without passing through
+// registers (LDS DMA: each lane's dword lands at the wave's LDS base plus 4
+// times its lane index).  Wave w copies the 64-dword chunks w, w + TPC/64,
+// ...; lds_copy_wait() and a barrier make the data visible to the block.
+// Both addresses must be 4-byte aligned.
+template <int TPC, class T, class U>
+__device__ __forceinline__ void lds_copy(const T *src, U *dst, int ndw) {
+  const uint32_t *s = reinterpret_cast<const uint32_t *>(src);
+  uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+  const int lane = threadIdx.x & 63;
+  for (int d0 = (int)(threadIdx.x >> 6) * 64; d0 < ndw; d0 += TPC)
+    if (d0 + lane < ndw)
+      __builtin_amdgcn_global_load_lds(s + d0 + lane,
+                                       (__attribute__((address_space(3))) void *)(d + d0), 4, 0,
+                                       0);
+}
+__device__ __forceinline__ void lds_copy_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // values the whole wave holds alike (read from LDS): kept in scalar registers
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ long long uni(long long x) {
+  const uint64_t b = (uint64_t)x;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  return (long long)(((uint64_t)hi << 32) | lo);
+}
 __device__ __forceinline__ double uni(double x) {
   const uint64_t b = (uint64_t)__double_as_longlong(x);
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
@@ -63,6 +87,111 @@ __device__ __forceinline__ double unif64(uint32_t a) { return ((double)a + 0.5) 
 // uniform in (0,1), exact in FP32 (top 24 bits of the word)
 __device__ __forceinline__ float unif32(uint32_t a) {
   return ((float)(a >> 8) + 0.5f) * 0x1p-24f;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-level exchanges on the VALU (DPP and the gfx950 permlane swaps), with
+// no trip through the LDS unit
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROWMASK = 0xF, bool BOUND = true>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xF, BOUND);
+}
+template <int CTRL, int ROWMASK = 0xF, bool BOUND = true>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = dpp_u32<CTRL, ROWMASK, BOUND>((uint32_t)b);
+  const uint32_t hi = dpp_u32<CTRL, ROWMASK, BOUND>((uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+constexpr int DPP_QP_1032 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int DPP_QP_2301 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114,
+              DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_WAVE_SHR1 = 0x138;
+constexpr int DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141;
+constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+
+// The two operands of level L (0..5) of a wave all-reduce: lanes pair up
+// within quads (L = 0, 1), then half rows and rows (L = 2, 3: mirrored lane
+// orders pair equal-valued groups), then rows of 16 (L = 4) and halves of 32
+// (L = 5: permlane swaps, which hand every lane the same two values in the
+// same order).  Combined with a commutative operation, every lane of a group
+// gets the same bits.
+template <int L>
+__device__ __forceinline__ void wave_pair(double x, double &a, double &b) {
+  if constexpr (L < 4) {
+    constexpr int C = L == 0 ? DPP_QP_1032
+                             : (L == 1 ? DPP_QP_2301 : (L == 2 ? DPP_ROW_HALF_MIRROR
+                                                               : DPP_ROW_MIRROR));
+    a = x;
+    b = dpp_f64<C>(x);
+  } else {
+    const uint64_t v = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    uint32_t a0, a1, b0, b1;
+    if constexpr (L == 4) {
+      const auto r0 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+      const auto r1 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+      a0 = r0[0], b0 = r0[1], a1 = r1[0], b1 = r1[1];
+    } else {
+      const auto r0 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+      const auto r1 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+      a0 = r0[0], b0 = r0[1], a1 = r1[0], b1 = r1[1];
+    }
+    a = __longlong_as_double((long long)(((uint64_t)a1 << 32) | a0));
+    b = __longlong_as_double((long long)(((uint64_t)b1 << 32) | b0));
+  }
+}
+template <int L, int N>
+__device__ __forceinline__ void wave_sum_level(double v[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double a, b;
+    wave_pair<L>(v[i], a, b);
+    v[i] = a + b;
+  }
+}
+// sum of N values over the wave, the same bits in every lane
+template <int N>
+__device__ __forceinline__ void wave_sum(double v[N]) {
+  wave_sum_level<0, N>(v);
+  wave_sum_level<1, N>(v);
+  wave_sum_level<2, N>(v);
+  wave_sum_level<3, N>(v);
+  wave_sum_level<4, N>(v);
+  wave_sum_level<5, N>(v);
+}
+
+// inclusive prefix sums over the wave: within rows of 16 by shifted adds,
+// then the totals of row 0 (into row 1), row 2 (into row 3) and rows 0-1
+// (into rows 2-3) by the row broadcasts
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+  x += dpp_u32<DPP_ROW_SHR1>(x);
+  x += dpp_u32<DPP_ROW_SHR2>(x);
+  x += dpp_u32<DPP_ROW_SHR4>(x);
+  x += dpp_u32<DPP_ROW_SHR8>(x);
+  x += dpp_u32<DPP_ROW_BCAST15, 0xA, false>(x);
+  x += dpp_u32<DPP_ROW_BCAST31, 0xC, false>(x);
+  return x;
+}
+__device__ __forceinline__ double wave_incl_scan(double x) {
+  x += dpp_f64<DPP_ROW_SHR1>(x);
+  x += dpp_f64<DPP_ROW_SHR2>(x);
+  x += dpp_f64<DPP_ROW_SHR4>(x);
+  x += dpp_f64<DPP_ROW_SHR8>(x);
+  x += dpp_f64<DPP_ROW_BCAST15, 0xA, false>(x);
+  x += dpp_f64<DPP_ROW_BCAST31, 0xC, false>(x);
+  return x;
+}
+// the value of the previous lane (0 in lane 0)
+__device__ __forceinline__ double wave_shr1(double x) { return dpp_f64<DPP_WAVE_SHR1>(x); }
+// the value of lane `lane` (a uniform index), in every lane
+__device__ __forceinline__ double wave_bcast(double x, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, lane);
+  const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // ---------------------------------------------------------------------------
@@ -80,6 +209,27 @@ __device__ __forceinline__ void csum_add(double &s, double &c, double x) {
   two_sum(s, x, t, e);
   s = t;
   c += e;
+}
+
+// level L of a compensated wave all-reduce of (s, c): TwoSum of the pair's
+// sums (its error term does not depend on the operand order) and the sum of
+// their compensations
+template <int L>
+__device__ __forceinline__ void wave_csum_level(double &s, double &c) {
+  double sa, sb, ca, cb, t, e;
+  wave_pair<L>(s, sa, sb);
+  wave_pair<L>(c, ca, cb);
+  two_sum(sa, sb, t, e);
+  s = t;
+  c = ca + cb + e;
+}
+__device__ __forceinline__ void wave_csum(double &s, double &c) {
+  wave_csum_level<0>(s, c);
+  wave_csum_level<1>(s, c);
+  wave_csum_level<2>(s, c);
+  wave_csum_level<3>(s, c);
+  wave_csum_level<4>(s, c);
+  wave_csum_level<5>(s, c);
 }
 
 template <int N>
@@ -101,17 +251,7 @@ __device__ __forceinline__ void block_csum(CSum<N> &v, double *red, double out[N
   const int wid = threadIdx.x / WAVE;
   constexpr int NW = TPC / WAVE;
 #pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      const double s2 = __shfl_xor(v.s[i], off);
-      const double c2 = __shfl_xor(v.c[i], off);
-      double t, e;
-      two_sum(v.s[i], s2, t, e);
-      v.s[i] = t;
-      v.c[i] = v.c[i] + c2 + e;
-    }
-  }
+  for (int i = 0; i < N; ++i) wave_csum(v.s[i], v.c[i]);
   if (NW == 1) {
 #pragma unroll
     for (int i = 0; i < N; ++i) out[i] = v.s[i] + v.c[i];
@@ -148,11 +288,7 @@ __device__ __forceinline__ void block_sum(double v[N], double *red, double out[N
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = threadIdx.x / WAVE;
   constexpr int NW = TPC / WAVE;
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off);
-  }
+  wave_sum<N>(v);
   if (NW == 1) {
 #pragma unroll
     for (int i = 0; i < N; ++i) out[i] = v[i];
@@ -182,16 +318,8 @@ __device__ __forceinline__ void block_sum_c1(double &s, double &c, double v[N], 
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = threadIdx.x / WAVE;
   constexpr int NW = TPC / WAVE;
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) {
-    const double s2 = __shfl_xor(s, off), c2 = __shfl_xor(c, off);
-    double t, e;
-    two_sum(s, s2, t, e);
-    s = t;
-    c = c + c2 + e;
-#pragma unroll
-    for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], off);
-  }
+  wave_csum(s, c);
+  wave_sum<N>(v);
   if (NW == 1) {
     out_c = s + c;
 #pragma unroll
@@ -234,18 +362,8 @@ __device__ __forceinline__ void block_sum_c2(double &s0, double &c0, double &s1,
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = threadIdx.x / WAVE;
   constexpr int NW = TPC / WAVE;
-#pragma unroll
-  for (int off = WAVE / 2; off > 0; off >>= 1) {
-    const double a2 = __shfl_xor(s0, off), ac = __shfl_xor(c0, off);
-    const double b2 = __shfl_xor(s1, off), bc = __shfl_xor(c1, off);
-    double t, e;
-    two_sum(s0, a2, t, e);
-    s0 = t;
-    c0 = c0 + ac + e;
-    two_sum(s1, b2, t, e);
-    s1 = t;
-    c1 = c1 + bc + e;
-  }
+  wave_csum(s0, c0);
+  wave_csum(s1, c1);
   if (NW == 1) {
     out0 = s0 + c0;
     out1 = s1 + c1;
@@ -328,12 +446,7 @@ __device__ __forceinline__ void block_exclusive_scan(uint32_t *a, int n, uint32_
   const int lo = t * PPT, hi = (lo + PPT < n) ? lo + PPT : n;
   uint32_t tot = 0;
   for (int idx = lo; idx < hi; ++idx) tot += a[idx];
-  uint32_t incl = tot;
-#pragma unroll
-  for (int d = 1; d < WAVE; d <<= 1) {
-    const uint32_t y = __shfl_up(incl, d);
-    if (lane >= d) incl += y;
-  }
+  const uint32_t incl = wave_incl_scan(tot);
   if (lane == WAVE - 1) wsum[wid] = incl;
   __syncthreads();
   uint32_t woff = 0, total = 0;

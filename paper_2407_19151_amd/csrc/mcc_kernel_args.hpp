@@ -32,6 +32,12 @@ struct SpeciesPrep {
 // prep_mode of CollideArgs
 enum : int32_t { PREP_NONE = 0, PREP_WRITE = 1, PREP_READ = 2 };
 
+// the collide kernels hand out cells from up to this many interleaved
+// queues, each with a claim and a finished-workgroup counter at the start of
+// its own WORK_STRIDE u32 (256 B)
+constexpr int WORK_QUEUES = 32;
+constexpr int WORK_STRIDE = 64;
+
 struct CollideArgs {
   const int64_t *offsets;  // [n_cells*S + 1]
   const double *w;
@@ -48,6 +54,8 @@ struct CollideArgs {
   CollConst coll[MCC_MAX_COLLISIONS];
   const int32_t *cell_list;     // work list of this size bucket
   const uint32_t *cell_count;   // device count of cell_list
+  uint32_t *work;               // [WORK_QUEUES * WORK_STRIDE] queue counters of the launch,
+                                // zero at launch and reset to zero by its end
   mcc_stats *stats;             // nullable
   int32_t *cell_corr;           // nullable
   int32_t *err;                 // device error word

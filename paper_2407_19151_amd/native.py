@@ -217,9 +217,10 @@ class Context:
             self.L.mcc_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        # at interpreter exit the HIP runtime may already be torn down
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # at interpreter exit the HIP runtime may already be torn down (and
+        # module globals such as sys cleared: hence the bound default)
+        if _finalizing():
             return
         try:
             self.close()
@@ -402,8 +403,8 @@ class Plan:
             self.ctx.L.mcc_plan_destroy(self.h)
             self.h = None
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        if _finalizing():
             return
         try:
             self.close()
