@@ -879,6 +879,16 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       MCC_PHASE(1);  // snapshot and shuffles
       // pre-scatter snapshot (Alg. 1, first step)
       double bx[GL ? 1 : PPT], by[GL ? 1 : PPT], bz[GL ? 1 : PPT];
+      if constexpr (!GL && !TAN) {
+        // every owned slot (those past n hold LDS contents nobody uses)
+#pragma unroll
+        for (int j = 0; j < PPT; ++j) {
+          const int e = t + j * TPC;
+          bx[j] = M.vx[e];
+          by[j] = M.vy[e];
+          bz[j] = M.vz[e];
+        }
+      } else
       for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
         if (e < n) {
           if constexpr (BIG) {
@@ -999,10 +1009,10 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       MCC_PHASE(3);  // momentum restore and energy sums
       if (!A.corr) continue;
 
-      auto part = [&](int e) {
-        return (e >= oa && e < oa + na) || (two && e >= ob && e < ob + nb);
-      };
-      auto mass_of = [&](int e) { return (e >= oa && e < oa + na) ? ma : mb; };
+      auto in_a = [&](int e) { return (unsigned)(e - oa) < (unsigned)na; };
+      auto in_b = [&](int e) { return two && (unsigned)(e - ob) < (unsigned)nb; };
+      auto part = [&](int e) { return in_a(e) || in_b(e); };
+      auto mass_of = [&](int e) { return in_a(e) ? ma : mb; };
 
       // momentum restore, Eq. (17): B = sum m_p (v_ps - v_bs) / sum m_p w_p;
       // v -= B w is applied in the energy pass below
@@ -1014,28 +1024,36 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         double P[6];
 #pragma unroll
         for (int i = 0; i < 6; ++i) P[i] = 0.0;
-        for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
-          if (e < n && part(e)) {
-            const double mp = mass_of(e) * M.w[e];
-            const double dx = mp * (M.vx[e] - SNAPX(j, e));
-            const double dy = mp * (M.vy[e] - SNAPY(j, e));
-            const double dz = mp * (M.vz[e] - SNAPZ(j, e));
-            if (dual && !(e >= oa && e < oa + na)) {
-              P[3] += dx;
-              P[4] += dy;
-              P[5] += dz;
-            } else {
-              P[0] += dx;
-              P[1] += dy;
-              P[2] += dz;
-            }
-            if constexpr (TAN) {
-              P[3] += mp * (M.tx[e] - M.btx[e]);
-              P[4] += mp * (M.ty[e] - M.bty[e]);
-              P[5] += mp * (M.tz[e] - M.btz[e]);
-            }
+        // branch-free where everything is in LDS: every owned slot is
+        // visited and non-members add nothing (slots past n lie in the LDS
+        // arrays, and what they hold is selected away)
+        auto mom = [&](int j, int e) {
+          const bool ia = in_a(e), ib = in_b(e);
+          const double mp = (ia ? ma : mb) * M.w[e];
+          const double dx = mp * (M.vx[e] - SNAPX(j, e));
+          const double dy = mp * (M.vy[e] - SNAPY(j, e));
+          const double dz = mp * (M.vz[e] - SNAPZ(j, e));
+          const bool to_a = ia || (ib && !dual), to_b = ib && dual;
+          P[0] += to_a ? dx : 0.0;
+          P[1] += to_a ? dy : 0.0;
+          P[2] += to_a ? dz : 0.0;
+          if constexpr (!TAN) {
+            P[3] += to_b ? dx : 0.0;
+            P[4] += to_b ? dy : 0.0;
+            P[5] += to_b ? dz : 0.0;
+          } else if (ia || ib) {
+            P[3] += mp * (M.tx[e] - M.btx[e]);
+            P[4] += mp * (M.ty[e] - M.bty[e]);
+            P[5] += mp * (M.tz[e] - M.btz[e]);
           }
-        });
+        };
+        if constexpr (!GL && W_LDS) {
+#pragma unroll
+          for (int j = 0; j < PPT; ++j) mom(j, t + j * TPC);
+        } else {
+          for_owned<TPC, PPT, !GL>(n, mom);
+        }
+        MCC_PHASE(10);  // momentum reduction
         double tot[6];
         if (dual)
           block_sum<TPC, 6>(P, red, tot);
@@ -1063,6 +1081,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
           });
         }
       }
+      MCC_PHASE(11);  // energy pass
       // energy violation, Eq. (18) (difference form), and the sums of Eq. (24)
       double dEs0, dEs1;
       double tdEs0 = 0.0, tdEs1 = 0.0;  // tangent form
@@ -1079,18 +1098,22 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
 #pragma unroll
         for (int i = 0; i < NE; ++i) Ev[i] = 0.0;
         const double c2 = A.c * A.c;
-        for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
-          if (e < n && part(e)) {
-            const bool isa = e >= oa && e < oa + na;
+        // mem: the particle takes part (with every slot visited, the sums
+        // select non-members away and only the stores are predicated)
+        auto energy = [&](int j, int e, bool mem) {
+          {
+            const bool isa = in_a(e);
             const bool sb = dual && !isa;
             const double we = M.w[e];
             const double mp = (isa ? ma : mb) * we;
             const double rbx = sb ? Bbx : Bx, rby = sb ? Bby : By, rbz = sb ? Bbz : Bz;
             const double vx = M.vx[e] - rbx * we, vy = M.vy[e] - rby * we,
                          vz = M.vz[e] - rbz * we;
-            M.vx[e] = vx;
-            M.vy[e] = vy;
-            M.vz[e] = vz;
+            if (mem) {
+              M.vx[e] = vx;
+              M.vy[e] = vy;
+              M.vz[e] = vz;
+            }
             const double ox = SNAPX(j, e), oy = SNAPY(j, e), oz = SNAPZ(j, e);
             const double dd = (vx - ox) * (vx + ox) + (vy - oy) * (vy + oy) + (vz - oz) * (vz + oz);
             double term, ke;
@@ -1104,14 +1127,10 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
               term = 0.5 * mp * dd;
               ke = 0.5 * mp * (vx * vx + vy * vy + vz * vz);
             }
-            if (sb)
-              csum_add(es1, ec1, term);
-            else
-              csum_add(es, ec, term);
-            if (isa)
-              Ev[0] += ke;
-            else
-              Ev[1] += ke;
+            csum_add(es, ec, (mem && !sb) ? term : 0.0);
+            if constexpr (DUAL) csum_add(es1, ec1, (mem && sb) ? term : 0.0);
+            Ev[0] += (mem && isa) ? ke : 0.0;
+            Ev[1] += (mem && !isa) ? ke : 0.0;
             if constexpr (TAN) {
               const double tvx = M.tx[e], tvy = M.ty[e], tvz = M.tz[e];
               const double dke = mp * (vx * tvx + vy * tvy + vz * tvz);
@@ -1122,7 +1141,19 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
                 Ev[4 % NE] += dke;
             }
           }
-        });
+        };
+        if constexpr (!GL && W_LDS && !TAN) {
+#pragma unroll
+          for (int j = 0; j < PPT; ++j) {
+            const int e = t + j * TPC;
+            energy(j, e, part(e));
+          }
+        } else {
+          for_owned<TPC, PPT, !GL>(n, [&](int j, int e) {
+            if (part(e)) energy(j, e, true);
+          });
+        }
+        MCC_PHASE(12);  // energy reduction
         dEs1 = 0.0;
         if constexpr (TAN) {
           double tot[NE];
@@ -1158,6 +1189,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         }
       }
 
+      MCC_PHASE(4);  // correction order
       // correction order per species (Alg. 1, optional sort), then the pair loop
       const int nsl = two ? 2 : 1;
       const uint16_t *O0 = L0, *O1 = L1;
