@@ -408,9 +408,7 @@ __device__ __forceinline__ void shuffle_species(const CellMem &M, int ns, int of
         const uint32_t ko = key[o], ki = key[i];
         return ko < ki || (ko == ki && o < i);
       },
-      M.slotbuf);
-  for (int q = t; q < ns; q += TPC) out[q] = (uint16_t)(out[q] + off);
-  __syncthreads();
+      M.slotbuf, [&](int i) -> int { return i + off; });
 }
 
 // The random permutations of both species of an inter-species collision in
@@ -451,9 +449,7 @@ __device__ __forceinline__ void shuffle_two(const CellMem &M, int na, int oa, in
         const uint32_t ko = key[o], ki = key[i];
         return ko < ki || (ko == ki && o < i);
       },
-      M.slotbuf);
-  for (int q = t; q < n; q += TPC) out[q] = (uint16_t)(out[q] + (q < na ? oa : ob - na));
-  __syncthreads();
+      M.slotbuf, [&](int i) -> int { return i < na ? oa + i : ob + (i - na); });
 }
 
 // Descending-weight order of ns particles, stable in list position (Alg. 1,
@@ -1221,9 +1217,12 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         if (resid0 == 0.0 && resid1 == 0.0) break;
         MCC_PHASE(5);  // pair energies
         // K of every pair; pairs are disjoint, so each K is the value the
-        // sequential loop of Alg. 1 sees
-        const int np0 = (resid0 != 0.0) ? na / 2 : 0;
-        const int np1 = (nsl == 2 && resid1 != 0.0) ? nb / 2 : 0;
+        // sequential loop of Alg. 1 sees.  In the plain non-relativistic
+        // form the cut-off computes K itself, 64 pairs at a time and only up
+        // to the cut pair (usually within the first 64).
+        constexpr bool KCUT = !REL && !TAN;
+        const int np0 = (!KCUT && resid0 != 0.0) ? na / 2 : 0;
+        const int np1 = (!KCUT && nsl == 2 && resid1 != 0.0) ? nb / 2 : 0;
         for (int m = t; m < np0 + np1; m += TPC) {
           const bool s1 = m >= np0;
           const int mm = s1 ? m - np0 : m;
@@ -1249,7 +1248,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             }
           }
         }
-        __syncthreads();
+        if constexpr (!KCUT) __syncthreads();
         MCC_PHASE(6);  // sequential cut-off loop
         if constexpr (REL) {
           // the running violation, in the paper's order (one lane per species):
@@ -1297,7 +1296,18 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             int ncut = 0, used = 0;
             for (int m0 = 0; m0 < np && absE != 0.0; m0 += WAVE) {
               const int m = m0 + lane;
-              const double lim = m < np ? A.fE * Kb[kb + m] : 0.0;
+              double lim = 0.0;
+              if (m < np) {
+                if constexpr (KCUT) {
+                  const uint16_t *O = s2 ? O1 : O0;
+                  const double ms = s2 ? mb : ma;
+                  const int p = O[2 * m], q = O[2 * m + 1];
+                  lim = A.fE * pair_K_nr(ms * M.w[p], ms * M.w[q], M.vx[p], M.vy[p], M.vz[p],
+                                         M.vx[q], M.vy[q], M.vz[q]);
+                } else {
+                  lim = A.fE * Kb[kb + m];
+                }
+              }
               const double P = wave_incl_scan(lim);
               const double Pprev = wave_shr1(P);  // (0 in lane 0)
               double tlim = 0.0, tP = 0.0, tPprev = 0.0;

@@ -468,19 +468,24 @@ __device__ __forceinline__ void block_exclusive_scan(uint32_t *a, int n, uint32_
   __syncthreads();
 }
 
+struct IdentityMap {
+  __device__ __forceinline__ int operator()(int i) const { return i; }
+};
+
 // ---------------------------------------------------------------------------
 // Bucket-rank sort in LDS.  Items 0..n-1 (n <= CAP) with a bucket function
 // that is non-decreasing in the sort order and a strict total order `less`.
-// out[pos] = item.  The result equals a full sort by `less`; the bucket only
+// out[pos] = map(item) (map: identity unless given).  The result equals a full sort by `less`; the bucket only
 // decides how much comparing is needed (about one item per bucket for
 // uniform keys).  cnt: u32[CAP+1]; mem: u16[CAP]; wsum: TPC/64 u32.
 // Returns the largest bucket occupancy (all threads).
 // ---------------------------------------------------------------------------
-template <int TPC, int PPT, bool G, class BucketF, class LessF>
+template <int TPC, int PPT, bool G, class BucketF, class LessF, class MapF = IdentityMap>
 __device__ __forceinline__ uint32_t bucket_rank_sort(int n, uint32_t *cnt, uint16_t *mem,
                                                     uint16_t *out, uint32_t *wsum,
                                                     uint32_t *maxocc, BucketF bucket,
-                                                    LessF less, uint32_t *slotbuf = nullptr) {
+                                                    LessF less, uint32_t *slotbuf = nullptr,
+                                                    MapF map = MapF()) {
   // G: many items per thread; the per-item slot goes to slotbuf[] (memory
   // private to the item's thread) instead of registers, and the bucket is
   // recomputed instead of kept
@@ -531,7 +536,7 @@ __device__ __forceinline__ uint32_t bucket_rank_sort(int n, uint32_t *cnt, uint1
       const int o = mem[m];
       if (o != i && less(o, i)) ++r;
     }
-    out[s0 + r] = (uint16_t)i;
+    out[s0 + r] = (uint16_t)map(i);
   };
   if constexpr (G) {
     for (int i = t; i < n; i += TPC) place(i, bucket(i));
