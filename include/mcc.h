@@ -110,8 +110,13 @@ const char *mcc_status_string(mcc_status s);
 
 /* Create a context on `device` enqueuing on `hip_stream` (NULL: the default
  * stream).  The context owns its workspace (cell work lists, error word,
- * large-cell scratch), grown on demand. */
+ * large-cell scratch, the collide kernels' cell-queue counters), grown on
+ * demand.  Work enqueued through one context must run in order: the calls of
+ * one context share that workspace, so they must not overlap on the device. */
 mcc_status mcc_create(mcc_ctx **ctx, int device, void *hip_stream);
+/* Enqueue later calls on `hip_stream`.  Work already enqueued on the previous
+ * stream must be complete (or ordered before the next call) first, since it
+ * shares the context's workspace. */
 mcc_status mcc_set_stream(mcc_ctx *ctx, void *hip_stream);
 void mcc_destroy(mcc_ctx *ctx);
 
