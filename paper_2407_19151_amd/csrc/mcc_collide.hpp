@@ -71,12 +71,14 @@ __device__ __forceinline__ void scatter_pair_nr(double *vx, double *vy, double *
   KR dx, dy, dz;
   rotate_delta<KR>(ux, uy, uz, st, oc, sp, cp, dx, dy, dz);
   // acceptance of the heavier particle, decided in FP64 in every mode
+  // (w_min / w_max: one division for either branch)
   const double u3 = unif64(r.w);
+  const double wratio = (wi < wj ? wi : wj) / wmax;
   bool ai = true, aj = true;
   if (wi < wj)
-    aj = u3 <= wi / wj;
+    aj = u3 <= wratio;
   else if (wj < wi)
-    ai = u3 <= wj / wi;
+    ai = u3 <= wratio;
   if (ai) {
     vx[I] = vix + fa * (double)dx;
     vy[I] = viy + fa * (double)dy;
@@ -931,6 +933,8 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       const bool abig = na >= nb;
       const int Nmax = abig ? na : nb, Nmin = abig ? nb : na;
       const double nmin = intra ? (double)(na - 1) : (double)Nmin;
+      // N_min / dV of each collision of the pass (once per pass, not per chain)
+      const double nmin_dv = nmin / dV, nmin_dv_b = (double)(nb - 1) / dV;
       const bool odd = intra && (na & 1);
       // Pairs that share a particle form a chain, run in order by one lane:
       // the odd triple (L0,L1),(L1,L2),(L2,L0); in an inter-species collision
@@ -949,7 +953,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         const int len = intra ? ((odds && ch == 0) ? 3 : 1) : (Nmax - ch + Nmin - 1) / Nmin;
         // the constants of the collision this chain belongs to
         const CollConst &Cs = s_cc[sb ? 1 : 0];
-        const double nmins = sb ? (double)(nb - 1) : nmin;
+        const double nmins_dv = sb ? nmin_dv_b : nmin_dv;
         const uint32_t c3s = sb ? c3pb : c3p;
         for (int r = 0; r < len; ++r) {
           int I, J;
@@ -980,7 +984,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             J = abig ? L1[ch] : L1[kk];
             kp = (uint32_t)kk;
           }
-          const double cf = Cs.coef * f * (nmins / dV);
+          const double cf = Cs.coef * f * nmins_dv;
           if constexpr (REL)
             scatter_pair_rel(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, ma, mb, A.c, A.method,
                              (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
