@@ -458,6 +458,11 @@ __device__ __forceinline__ void shuffle_two(const CellMem &M, int na, int oa, in
 // optional step): the particles are L[0..ns) (cell-local indices), or, with
 // L == nullptr, off, off+1, ..., off+ns-1.  O receives cell-local indices.
 // lo < hi are the bit patterns of the smallest and largest weight.
+// weight order: a bucket above this occupancy switches to the per-value pass
+// (at most MAX_WEIGHT_VALUES distinct values among the crowded ties)
+constexpr uint32_t OCC_LIMIT = 48;
+constexpr int MAX_WEIGHT_VALUES = 32;
+
 template <int TPC, int PPT, bool G>
 __device__ __forceinline__ void weight_sort(const CellMem &M, int ns, const uint16_t *L, int off,
                                             uint16_t *O, uint64_t lo, uint64_t hi,
@@ -477,16 +482,47 @@ __device__ __forceinline__ void weight_sort(const CellMem &M, int ns, const uint
         const uint32_t k = (uint32_t)((double)(hi - b) * scale);
         return k < (uint32_t)ns ? k : (uint32_t)(ns - 1);
       },
-      before, M.slotbuf);
-  if (occ > 48) {
-    // few distinct weights: the comparison count per bucket grows as its
-    // occupancy squared; a bitonic network is cheaper here
-    int P = 1;
-    while (P < ns) P <<= 1;
-    for (int i = t; i < P; i += TPC) M.mem[i] = i < ns ? (uint16_t)i : (uint16_t)0xFFFF;
-    __syncthreads();
-    bitonic_sort_ids<TPC>(M.mem, P, before);
-    for (int q = t; q < ns; q += TPC) O[q] = M.mem[q];
+      before, M.slotbuf, IdentityMap(), OCC_LIMIT);
+  if (occ > OCC_LIMIT) {
+    // Crowded buckets come from ties, usually among few distinct weights:
+    // ranking inside a bucket would cost its occupancy squared.  Instead,
+    // one pass per distinct weight value, largest first, appends the items
+    // of that weight in list order (each thread scans a contiguous chunk of
+    // the list, so thread order is list order).
+    auto wbits = [&](int q) -> uint64_t {
+      return (uint64_t)__double_as_longlong(w[item(q)]);  // (w > 0: bit order = value order)
+    };
+    const int C = (ns + TPC - 1) / TPC;
+    const int q0 = t * C, q1 = q0 + C < ns ? q0 + C : ns;
+    uint64_t *redu = reinterpret_cast<uint64_t *>(M.cnt);  // (free: the sort stopped early)
+    uint64_t cur = hi;
+    int placed = 0;
+    for (int round = 0; round < MAX_WEIGHT_VALUES && placed < ns; ++round) {
+      uint32_t c = 0;
+      for (int q = q0; q < q1; ++q) c += wbits(q) == cur ? 1u : 0u;
+      uint32_t tot;
+      uint32_t pos = (uint32_t)placed + block_excl_scan1<TPC, G>(c, wsum, tot);
+      uint64_t lo1[1] = {~0ull}, nxt[1] = {0ull};
+      for (int q = q0; q < q1; ++q) {
+        const uint64_t b = wbits(q);
+        if (b == cur)
+          O[pos++] = (uint16_t)q;
+        else if (b < cur && b > nxt[0])
+          nxt[0] = b;
+      }
+      block_minmax_u64<TPC, 1, G>(lo1, nxt, redu);
+      placed += (int)tot;
+      cur = nxt[0];
+    }
+    if (placed < ns) {
+      // many distinct values among the ties: a bitonic network
+      int P = 1;
+      while (P < ns) P <<= 1;
+      for (int i = t; i < P; i += TPC) M.mem[i] = i < ns ? (uint16_t)i : (uint16_t)0xFFFF;
+      __syncthreads();
+      bitonic_sort_ids<TPC>(M.mem, P, before);
+      for (int q = t; q < ns; q += TPC) O[q] = M.mem[q];
+    }
     __syncthreads();
   }
   for (int q = t; q < ns; q += TPC) O[q] = (uint16_t)item(O[q]);

@@ -472,12 +472,38 @@ struct IdentityMap {
   __device__ __forceinline__ int operator()(int i) const { return i; }
 };
 
+// Exclusive prefix sum of one value per thread, in thread order; `total`
+// receives the sum (all threads).  wsum: TPC/64 u32.  Ends with a barrier.
+template <int TPC, bool G>
+__device__ __forceinline__ uint32_t block_excl_scan1(uint32_t x, uint32_t *wsum,
+                                                     uint32_t &total) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wid = threadIdx.x / WAVE;
+  constexpr int NW = TPC / WAVE;
+  const uint32_t incl = wave_incl_scan(x);
+  if (lane == WAVE - 1) wsum[wid] = incl;
+  __syncthreads();
+  uint32_t woff = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const uint32_t v = wsum[w];
+    if (w < wid) woff += v;
+    tot += v;
+  }
+  total = tot;
+  __syncthreads();
+  return woff + incl - x;
+}
+
 // ---------------------------------------------------------------------------
 // Bucket-rank sort in LDS.  Items 0..n-1 (n <= CAP) with a bucket function
 // that is non-decreasing in the sort order and a strict total order `less`.
 // out[pos] = map(item) (map: identity unless given).  The result equals a full sort by `less`; the bucket only
 // decides how much comparing is needed (about one item per bucket for
 // uniform keys).  cnt: u32[CAP+1]; mem: u16[CAP]; wsum: TPC/64 u32.
+// occ_limit: a bucket fuller than this ends the sort right after the
+// counting (out unset): the caller orders such inputs another way, since
+// ranking within a bucket costs its occupancy squared.
 // Returns the largest bucket occupancy (all threads).
 // ---------------------------------------------------------------------------
 template <int TPC, int PPT, bool G, class BucketF, class LessF, class MapF = IdentityMap>
@@ -485,7 +511,8 @@ __device__ __forceinline__ uint32_t bucket_rank_sort(int n, uint32_t *cnt, uint1
                                                     uint16_t *out, uint32_t *wsum,
                                                     uint32_t *maxocc, BucketF bucket,
                                                     LessF less, uint32_t *slotbuf = nullptr,
-                                                    MapF map = MapF()) {
+                                                    MapF map = MapF(),
+                                                    uint32_t occ_limit = 0xFFFFFFFFu) {
   // G: many items per thread; the per-item slot goes to slotbuf[] (memory
   // private to the item's thread) instead of registers, and the bucket is
   // recomputed instead of kept
@@ -519,6 +546,7 @@ __device__ __forceinline__ uint32_t bucket_rank_sort(int n, uint32_t *cnt, uint1
   // read here, between barriers: the next call resets *maxocc only after this
   // call's last barrier, so every thread returns the same value
   const uint32_t occ = *maxocc;
+  if (occ > occ_limit) return occ;  // (uniform: read between barriers)
   if constexpr (G) {
     for (int i = t; i < n; i += TPC) mem[cnt[bucket(i)] + slotbuf[i]] = (uint16_t)i;
   } else {

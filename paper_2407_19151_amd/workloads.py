@@ -278,6 +278,79 @@ def config5(n_cells: int = 1024, ppc: int = 256, Te0: float = 2.0, Ti0: float = 
     return _scale_electron_density(wl)
 
 
+# SI constants (CODATA 2018) for the paper's own test problems
+E_CHARGE = 1.602176634e-19      # C
+M_ELECTRON = 9.1093837015e-31   # kg
+M_U = 1.66053906660e-27         # kg
+EPS0_SI = 8.8541878128e-12      # F/m
+
+# Test 1 of the numerical tests (Sec. 5.1 and its table): two populations of
+# fully ionized carbon 12 in one species; per case N_A, N_B per cell, dt [s]
+# and f_E (the weight ratio follows from the densities and counts)
+PAPER_T1_CASES = {
+    "T1a": (400, 4000, 50e-15, 0.05),
+    "T1b": (400, 400, 50e-15, 0.05),
+    "T1c": (4000, 400, 15e-15, 0.02),
+    "T1d": (200, 8000, 50e-15, 0.05),
+}
+
+
+def paper_test1(case: str = "T1b", n_cells: int = 180, seed_data: int = 11,
+                method: int = N97, cell_volume: float = 1e-18) -> Workload:
+    """Test 1 in SI units: populations A (n = 1e19 cm^-3, T = 500 eV,
+    U = +655 km/s along x) and B (n = 1e20 cm^-3, T = 500 eV, at rest) of
+    C^6+ (m = 12 m_u - 6 m_e), lnL = 10, quasi-0D (cells independent).  Each
+    cell holds N_A particles of A, then N_B of B, all one species; weights
+    are physical particles per macro-particle, n * dV / N.  extra["population"]
+    is 0 for A and 1 for B."""
+    n_a, n_b, dt, f_e = PAPER_T1_CASES[case]
+    m = 12.0 * M_U - 6.0 * M_ELECTRON
+    q = 6.0 * E_CHARGE
+    dens = (1e25, 1e26)            # m^-3
+    temp_ev = (500.0, 500.0)
+    drift = (655e3, 0.0)           # m/s along x
+    counts = np.full((n_cells, 1), n_a + n_b, dtype=np.int64)
+    rng = np.random.Generator(np.random.PCG64(seed_data))
+    n = n_cells * (n_a + n_b)
+    pop = np.tile(np.concatenate([np.zeros(n_a, np.int8), np.ones(n_b, np.int8)]), n_cells)
+    w = np.empty(n)
+    v = np.empty((3, n))
+    for k, npk in enumerate((n_a, n_b)):
+        sel = pop == k
+        w[sel] = dens[k] * cell_volume / npk
+        sig = math.sqrt(temp_ev[k] * E_CHARGE / m)
+        v[:, sel] = rng.normal(0.0, sig, size=(3, int(sel.sum())))
+        v[0, sel] += drift[k]
+
+    offsets = np.zeros(n_cells + 1, dtype=np.int64)
+    np.cumsum(counts.reshape(-1), out=offsets[1:])
+    wl = Workload(name="paper Test 1 (%s), %d cells x (%d A + %d B) C6+" % (case, n_cells, n_a, n_b),
+                  n_cells=n_cells, n_species=1, offsets=offsets,
+                  cells=np.repeat(np.arange(n_cells, dtype=np.int32), n_a + n_b),
+                  species=np.zeros(n, dtype=np.int32), w=w, vx=v[0].copy(), vy=v[1].copy(),
+                  vz=v[2].copy(), mass=np.array([m]), charge=np.array([q]),
+                  collisions=[(0, 0)], dt=dt, coulomb_log=10.0, method=method,
+                  eps0=EPS0_SI, cell_volume=cell_volume, f_E=f_e,
+                  seed=PHILOX_SEED_BASE + 0x71, steps=1)
+    wl.extra = dict(population=pop, densities=dens, temperatures_ev=temp_ev, drifts=drift)
+    return wl
+
+
+def population_moments(wl: Workload, v: np.ndarray) -> dict:
+    """Per population of a paper test: density-weighted mean x-velocity [m/s]
+    and temperature [eV] about that mean (all cells together)."""
+    pop = wl.extra["population"]
+    m = wl.mass[wl.species]
+    out = {}
+    for k in np.unique(pop):
+        sel = pop == k
+        wk = wl.w[sel]
+        mean = (v[:, sel] * wk).sum(1) / wk.sum()
+        d2 = ((v[:, sel] - mean[:, None]) ** 2).sum(0)
+        out[int(k)] = (mean[0], (m[sel] * wk * d2).sum() / (3.0 * wk.sum()) / E_CHARGE)
+    return out
+
+
 def standard_normal_state(wl: Workload, seed_data: int) -> np.ndarray:
     """Fixed xi ~ N(0,1)^{3 x n} for the reparameterized initial state
     v0 = sqrt(T0/m) xi of the differentiated relaxation."""

@@ -46,7 +46,8 @@ def custom_workload(sizes, seed=0, masses=(1.0, 100.0), charges=(-1.0, 1.0),
                     relativistic=False, c=math.inf, dt=None):
     """Cells with the given per-species counts [(n_e, n_i), ...]; weights:
     'mixed' (equal electrons, log-uniform ions), 'lognormal', 'equal' or
-    'two' (two weight classes per species)."""
+    'two' (two weight classes per species) or 'clustered' (40 values within a
+    few ulp, plus an outlier)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     S = len(masses)
     counts = np.array(sizes, dtype=np.int64).reshape(-1, S)
@@ -67,6 +68,14 @@ def custom_workload(sizes, seed=0, masses=(1.0, 100.0), charges=(-1.0, 1.0),
         w = np.ones(n)
     elif weight_mode == "lognormal":
         w = rng.lognormal(0.0, 1.0, n)
+    elif weight_mode == "clustered":
+        # 40 distinct weights within a few ulp of 1 and one heavy outlier per
+        # species: all of them share one bucket of the weight order
+        w = 1.0 + (rng.integers(0, 40, n) * 2.0 ** -45)
+        for s in range(S):
+            first = np.nonzero(species == s)[0]
+            if first.size:
+                w[first[0]] = 100.0
     elif weight_mode == "two":
         w = np.where(rng.uniform(size=n) < 0.7, 1.0, 1e-2)
     else:

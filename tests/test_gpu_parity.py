@@ -94,10 +94,11 @@ def test_parity_large_global_scratch_cells(ctx):
     _parity(ctx, wl, 2)
 
 
-@pytest.mark.parametrize("wmode", ["lognormal", "two", "equal"])
+@pytest.mark.parametrize("wmode", ["lognormal", "two", "clustered", "equal"])
 def test_parity_weight_orders(ctx, wmode):
-    """Distinct weights (bucket order), two weight classes (bitonic
-    fallback), equal weights (shuffled order)."""
+    """Distinct weights (bucket order), two weight classes (crowded bucket:
+    one pass per weight value), 40 clustered values (crowded bucket with too
+    many values: bitonic network), equal weights (shuffled order)."""
     sizes = [(300, 200), (97, 64), (512, 512), (40, 3)]
     wl = custom_workload(sizes, seed=6, weight_mode=wmode)
     _parity(ctx, wl, 0)
