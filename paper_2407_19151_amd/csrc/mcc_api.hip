@@ -56,7 +56,6 @@ using namespace mcc;
 namespace {
 
 constexpr int CANON_BIG_GRID = 16;
-constexpr int BIG32K_GRID = 32;
 
 struct DevBuf {
   void *p = nullptr;
@@ -122,6 +121,7 @@ struct mcc_plan {
   int mode = 0;
   int32_t n_cells = 0;
   int variant[NBUCKET] = {};
+  uint32_t hcount[NBUCKET] = {};  // cells per bucket (fixed for the plan)
   DevBuf lists, counts, step;
   DevBuf prep, prep_word;  // weight data of the bound population (PREP_READ)
   mcc_stats *stats = nullptr;
@@ -240,7 +240,7 @@ bool ensure_lists(mcc_ctx *ctx, DevBuf &lists, DevBuf &counts, int32_t n_cells) 
 // global-layout variants: persistent grid and per-workgroup scratch
 int grid_of(mcc_ctx *ctx, int mode, int v) {
   const Variant V = variant_of(mode, v);
-  if (V.layout == 2) return V.cap > 4096 ? BIG32K_GRID : ctx->n_cu;
+  if (V.layout == 2) return ctx->n_cu;
   return ctx->grid[mode][v];
 }
 
@@ -248,7 +248,7 @@ bool ensure_big(mcc_ctx *ctx, int mode, int v) {
   const Variant V = variant_of(mode, v);
   if (V.layout != 2) return true;
   const uint64_t stride = big_stride_bytes(V.cap, mode == MODE_TAN);
-  if (V.cap > 4096) return ctx->big32k.ensure(stride * BIG32K_GRID);
+  if (V.cap > 4096) return ctx->big32k.ensure(stride * (uint64_t)ctx->n_cu);
   return ctx->big4k.ensure(stride * (uint64_t)ctx->n_cu);
 }
 
@@ -285,10 +285,13 @@ mcc_status launch_bucket(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_
 }
 
 // enqueue the collide kernels of all buckets, largest cells first
+// (host_counts: the buckets' cell counts when known on the host; empty
+// buckets are then not launched)
 mcc_status launch_buckets(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_t n_cells,
                           const int32_t *lists, const uint32_t *counts, const int *variant,
-                          hipStream_t stream) {
+                          hipStream_t stream, const uint32_t *host_counts = nullptr) {
   for (int b = NBUCKET - 1; b >= 0; --b) {
+    if (host_counts && host_counts[b] == 0) continue;
     const int v = variant[b] >= 0 ? variant[b] : default_variant(mode, b);
     const mcc_status st = launch_bucket(ctx, base, mode, n_cells, lists, counts, b, v, stream);
     if (st != MCC_OK) return st;
@@ -603,7 +606,7 @@ static mcc_status plan_enqueue_step(mcc_plan *pl, hipStream_t s) {
   if (pl->stats) HIP_TRY(launch_zero_stats(pl->stats, s));
   mcc_status st = launch_buckets(pl->ctx, pl->args, pl->mode, pl->n_cells,
                                  pl->lists.as<int32_t>(), pl->counts.as<uint32_t>(), pl->variant,
-                                 s);
+                                 s, pl->hcount);
   if (st != MCC_OK) return st;
   HIP_TRY(launch_inc_u64(pl->step.as<uint64_t>(), s));
   return MCC_OK;
@@ -645,6 +648,8 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
     e = launch_bucket_cells(offsets, n_cells, n_species, n, pl->lists.as<int32_t>(),
                             pl->counts.as<uint32_t>(), cell_corr_pairs, ctx->err, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->hcount, pl->counts.p, sizeof(pl->hcount), hipMemcpyDeviceToHost);
   if (e != hipSuccess) {
     mcc_plan_destroy(pl);
     return from_hip(e);
@@ -741,7 +746,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
     W.stats = nullptr;
     W.cell_corr = nullptr;
     st = launch_buckets(ctx, W, pl->mode, n_cells, pl->lists.as<int32_t>(),
-                        pl->counts.as<uint32_t>(), pl->variant, s);
+                        pl->counts.as<uint32_t>(), pl->variant, s, pl->hcount);
     if (st == MCC_OK) st = from_hip(hipStreamSynchronize(s));
     if (st != MCC_OK) {
       mcc_plan_destroy(pl);
