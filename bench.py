@@ -12,6 +12,8 @@ line.
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--autotune]
   python bench.py --copy-calibration MIB   (reference copy for the byte counters)
   python bench.py --paper-test1            (the paper's Test 1 cases: one JSON line each)
+  python bench.py --paper-test2            (the paper's Test 2 cases: one JSON line each)
+  python bench.py --paper-test3            (the paper's Test 3 cases: one JSON line each)
 """
 import argparse
 import hashlib
@@ -47,6 +49,10 @@ def parse():
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
     ap.add_argument("--paper-test1", action="store_true",
                     help="only time the paper's Test 1 cases (SI units, 180 cells, FP64) and exit")
+    ap.add_argument("--paper-test2", action="store_true",
+                    help="only time the paper's Test 2 cases (SI units, 180 cells, FP64) and exit")
+    ap.add_argument("--paper-test3", action="store_true",
+                    help="only time the paper's Test 3 cases (SI units, 1600 cells, FP64) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (the "
                          "reference reading for the HBM byte counters) and exit")
@@ -166,16 +172,21 @@ def cpu_baseline(seconds):
                        "N97, FP64, correction on), one thread" % (steps, sub.n))
 
 
-def paper_test1(steps, warmup):
-    """Step time and throughput of each Test 1 case (a plan, graph replays)."""
+def paper_tests(which, steps, warmup):
+    """Step time and throughput of each case of the paper's Test 1, 2 or 3
+    (a plan, graph replays)."""
     import torch
     from paper_2407_19151_amd import native, runner
     from paper_2407_19151_amd import workloads as W
     ctx = native.Context(0)
-    for case in sorted(W.PAPER_T1_CASES):
-        wl = W.paper_test1(case)
+    cases, make = {1: (W.PAPER_T1_CASES, W.paper_test1), 2: (W.PAPER_T2_CASES, W.paper_test2),
+                   3: (W.PAPER_T3_CASES, W.paper_test3)}[which]
+    for case in sorted(cases):
+        wl = make(case)
+        corr = int((wl.extra or {}).get("moment_correction", True))
         dw = runner.DeviceWorkload(wl)
-        plan = runner.make_plan(ctx, dw, autotune=False)
+        plan = runner.make_plan(ctx, dw, params=runner.params_for(wl, moment_correction=corr),
+                                autotune=False)
         ms, _ = time_plan(plan, steps, warmup, first_step=0)
         desc = json.loads(plan.describe())
         plan.close()
@@ -183,7 +194,7 @@ def paper_test1(steps, warmup):
         print(json.dumps({"workload": wl.name, "ms_per_step": ms,
                           "particle_collisions_per_s": wl.particle_collisions_per_step() / (ms * 1e-3),
                           "variant": "%dx%d layout %d" % (b["tpc"], b["cap"], b["layout"]),
-                          "steps": steps, "dtype": "f64"}), flush=True)
+                          "moment_correction": bool(corr), "steps": steps, "dtype": "f64"}), flush=True)
         del dw
         torch.cuda.empty_cache()
 
@@ -193,8 +204,8 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.paper_test1:
-        paper_test1(args.steps, args.warmup)
+    if args.paper_test1 or args.paper_test2 or args.paper_test3:
+        paper_tests(1 if args.paper_test1 else 2 if args.paper_test2 else 3, args.steps, args.warmup)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: there is no multi-GPU path here (cells shard "

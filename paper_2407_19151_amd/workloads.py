@@ -336,6 +336,145 @@ def paper_test1(case: str = "T1b", n_cells: int = 180, seed_data: int = 11,
     return wl
 
 
+# Test 2 (Sec. 5.2 and its table): A in species alpha, B and C in species
+# beta; per case N_A, N_B, N_C per cell (dt = 50 fs, f_E = 0.05 throughout)
+PAPER_T2_CASES = {
+    "T2a": (400, 4000, 200),
+    "T2b": (400, 4000, 800),
+    "T2c": (400, 800, 4000),
+    "T2d": (4000, 500, 100),
+    "T2e": (4000, 100, 500),
+}
+
+
+def _populations(rng, m, counts, dens, temps_ev, drifts, cell_volume, n_cells):
+    """Per population k: N_k particles per cell, weights n_k dV / N_k,
+    Maxwellian velocities about a drift along x."""
+    out = []
+    for npk, n_k, t_k, u_k in zip(counts, dens, temps_ev, drifts):
+        total = npk * n_cells
+        sig = math.sqrt(t_k * E_CHARGE / m)
+        v = rng.normal(0.0, sig, size=(3, total))
+        v[0] += u_k
+        out.append((np.full(total, n_k * cell_volume / npk), v))
+    return out
+
+
+def paper_test2(case: str = "T2a", n_cells: int = 180, seed_data: int = 12,
+                method: int = N97, cell_volume: float = 1e-18, scale: int = 1) -> Workload:
+    """Test 2 in SI units: populations A (species alpha: n = 1e19 cm^-3,
+    U = +655 km/s), B and C (species beta: n = 1e20 cm^-3 at rest, and the
+    low-density C at U = -655 km/s), all C^6+ at T = 500 eV, lnL = 10,
+    dt = 50 fs, f_E = 0.05.  n_C = 5e18 cm^-3: every row of the paper's table
+    gives n_A : n_B : n_C = 2 : 20 : 1 through its counts and weight ratios.
+    Collisions (alpha, alpha), (beta, beta), (alpha, beta).
+    extra["population"] is 0, 1, 2 for A, B, C.  `scale` multiplies every
+    per-cell count (the weight ratios stay those of the table)."""
+    n_a, n_b, n_c = (scale * k for k in PAPER_T2_CASES[case])
+    m = 12.0 * M_U - 6.0 * M_ELECTRON
+    q = 6.0 * E_CHARGE
+    dens = (1e25, 1e26, 5e24)        # m^-3
+    temps = (500.0, 500.0, 500.0)
+    drifts = (655e3, 0.0, -655e3)
+    rng = np.random.Generator(np.random.PCG64(seed_data))
+    pops = _populations(rng, m, (n_a, n_b, n_c), dens, temps, drifts, cell_volume, n_cells)
+    per_cell = [n_a, n_b + n_c]      # species alpha, beta
+    n = n_cells * (n_a + n_b + n_c)
+    w = np.empty(n)
+    v = np.empty((3, n))
+    pop = np.empty(n, np.int8)
+    species = np.empty(n, np.int32)
+    cells = np.empty(n, np.int32)
+    pos = 0
+    cursor = [0, 0, 0]
+    for c in range(n_cells):
+        for k, npk in ((0, n_a), (1, n_b), (2, n_c)):
+            sl = slice(pos, pos + npk)
+            src = slice(cursor[k], cursor[k] + npk)
+            w[sl] = pops[k][0][src]
+            v[:, sl] = pops[k][1][:, src]
+            pop[sl] = k
+            species[sl] = 0 if k == 0 else 1
+            cells[sl] = c
+            cursor[k] += npk
+            pos += npk
+    offsets = np.zeros(2 * n_cells + 1, dtype=np.int64)
+    np.cumsum(np.tile(per_cell, n_cells), out=offsets[1:])
+    wl = Workload(name="paper Test 2 (%s), %d cells x (%d A | %d B + %d C) C6+"
+                  % (case, n_cells, n_a, n_b, n_c),
+                  n_cells=n_cells, n_species=2, offsets=offsets, cells=cells, species=species,
+                  w=w, vx=v[0].copy(), vy=v[1].copy(), vz=v[2].copy(),
+                  mass=np.array([m, m]), charge=np.array([q, q]),
+                  collisions=[(0, 0), (1, 1), (0, 1)], dt=50e-15, coulomb_log=10.0,
+                  method=method, eps0=EPS0_SI, cell_volume=cell_volume, f_E=0.05,
+                  seed=PHILOX_SEED_BASE + 0x72, steps=1)
+    wl.extra = dict(population=pop, densities=dens, temperatures_ev=temps, drifts=drifts)
+    return wl
+
+
+# Test 3 (Sec. 5.3): N_i, N_e per cell and whether the moment correction runs
+PAPER_T3_CASES = {
+    "T3a": (512, 3072, True),
+    "T3b": (512, 512, False),
+    "T3c": (512, 512, True),
+}
+PAPER_T3_DX = 1.3285e-9  # m, the grid spacing
+
+
+def paper_test3(case: str = "T3a", n_cells: int = 1600, seed_data: int = 13,
+                method: int = N97) -> Workload:
+    """Test 3 in SI units: electron-ion thermalization of fully ionized
+    carbon (Z = 6, M_i = 12 m_u - 6 m_e), non-drifting Maxwellians with
+    n_i = 1e23 cm^-3, T_i = 50 eV, n_e = 6e23 cm^-3, T_e = 150 eV; lnL = 3,
+    dt = 3.54e-4 fs, on the 40 x 40 grid of cells of side 1.3285 nm (taken as
+    cubes).  Species 0 is the electrons, 1 the ions; collisions (e, e),
+    (i, i), (e, i).  T3a weighs both species equally (N_e = 6 N_i); T3b and
+    T3c use N_e = N_i, so w_e = 6 w_i, without and with the correction
+    (extra["moment_correction"])."""
+    n_i, n_e, corr = PAPER_T3_CASES[case]
+    m_i = 12.0 * M_U - 6.0 * M_ELECTRON
+    dv = PAPER_T3_DX ** 3
+    rng = np.random.Generator(np.random.PCG64(seed_data))
+    (w_e, v_e), (w_i, v_i) = _populations(rng, M_ELECTRON, (n_e,), (6e29,), (150.0,), (0.0,),
+                                          dv, n_cells) + \
+        _populations(rng, m_i, (n_i,), (1e29,), (50.0,), (0.0,), dv, n_cells)
+    per = n_e + n_i
+    n = n_cells * per
+    w = np.empty(n)
+    v = np.empty((3, n))
+    lay = np.concatenate([np.zeros(n_e, np.int32), np.ones(n_i, np.int32)])
+    species = np.tile(lay, n_cells)
+    cells = np.repeat(np.arange(n_cells, dtype=np.int32), per)
+    ie = species == 0
+    w[ie], w[~ie] = w_e, w_i
+    v[:, ie], v[:, ~ie] = v_e, v_i
+    offsets = np.zeros(2 * n_cells + 1, dtype=np.int64)
+    np.cumsum(np.tile([n_e, n_i], n_cells), out=offsets[1:])
+    wl = Workload(name="paper Test 3 (%s), %d cells x (%d e + %d C6+)" % (case, n_cells, n_e, n_i),
+                  n_cells=n_cells, n_species=2, offsets=offsets, cells=cells, species=species,
+                  w=w, vx=v[0].copy(), vy=v[1].copy(), vz=v[2].copy(),
+                  mass=np.array([M_ELECTRON, m_i]), charge=np.array([-E_CHARGE, 6.0 * E_CHARGE]),
+                  collisions=[(0, 0), (1, 1), (0, 1)], dt=3.54e-19, coulomb_log=3.0,
+                  method=method, eps0=EPS0_SI, cell_volume=dv, f_E=0.05,
+                  seed=PHILOX_SEED_BASE + 0x73, steps=1)
+    wl.extra = dict(moment_correction=corr, densities=(6e29, 1e29), temperatures_ev=(150.0, 50.0))
+    return wl
+
+
+def species_temperatures(wl: Workload, v: np.ndarray) -> Tuple[float, float]:
+    """Weighted temperatures [eV] of species 0 and 1 over the whole grid,
+    each about its own mean velocity."""
+    out = []
+    for s in (0, 1):
+        sel = wl.species == s
+        w = wl.w[sel]
+        vv = v[:, sel]
+        u = (vv * w).sum(1) / w.sum()
+        d = vv - u[:, None]
+        out.append(wl.mass[s] * (w * (d * d).sum(0)).sum() / w.sum() / 3.0 / E_CHARGE)
+    return out[0], out[1]
+
+
 def population_moments(wl: Workload, v: np.ndarray) -> dict:
     """Per population of a paper test: density-weighted mean x-velocity [m/s]
     and temperature [eV] about that mean (all cells together)."""
