@@ -21,6 +21,8 @@ LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 TA77 = 0
 N97 = 1
+ORDER_N = 0
+NXN = 1
 
 _lib = None
 
@@ -70,11 +72,11 @@ def lib():
         L.oracle_scatter_pair.restype = None
         L.oracle_collide_sorted.argtypes = (
             [i64, i32, i32, P, P, P, i32, P, P, P, P, P, P, P, f64, f64, f64, u64, u64,
-             i32, i32, i32, i32, i32, i32, f64, f64, f64, P, i32, P, P, P])
+             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, i32, P, P, P])
         L.oracle_collide_sorted.restype = C.c_int
         L.oracle_collide.argtypes = (
             [i64, P, P, i32, i32, P, P, i32, P, P, P, P, P, P, P, f64, f64, f64, u64, u64,
-             i32, i32, i32, i32, i32, i32, f64, f64, f64, P, P, P])
+             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, P, P])
         L.oracle_collide.restype = C.c_int
         L.oracle_collide_sorted_traced.argtypes = (
             [i64, i32, i32, P, P, P, i32, P, P, P, P, P, P, f64, f64, f64, u64, u64,
@@ -174,8 +176,9 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
                    correction=True, sort_by_weight=True, max_passes=1,
                    keep_on_fail=False, f_E=0.05, eps0=1.0, c=math.inf,
                    cell_volume=1.0, cells: Optional[Sequence[int]] = None,
-                   n_cells: Optional[int] = None) -> dict:
-    """One step on (cell, species)-grouped arrays; vx, vy, vz updated in place."""
+                   n_cells: Optional[int] = None, pairing: int = ORDER_N) -> dict:
+    """One step on (cell, species)-grouped arrays; vx, vy, vz updated in place.
+    pairing: ORDER_N (Sec. 3.2) or NXN (every pair once, Sec. 3.1)."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     mass = _f64(mass)
     charge = _f64(charge)
@@ -198,8 +201,8 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
     rc = lib().oracle_collide_sorted(
         w.shape[0], n_cells, S, _p(offsets), _p(mass), _p(charge), len(collisions),
         _p(ca), _p(cb), _p(w), _p(vx), _p(vy), _p(vz), _p(cv), cvs, dt, coulomb_log,
-        seed, step, method, int(relativistic), int(correction), int(sort_by_weight),
-        max_passes, int(keep_on_fail), f_E, eps0, c, _p(cl),
+        seed, step, method, int(pairing), int(relativistic), int(correction),
+        int(sort_by_weight), max_passes, int(keep_on_fail), f_E, eps0, c, _p(cl),
         0 if cl is None else cl.shape[0], _p(counters), _p(diag), _p(ccp))
     if rc != 0:
         raise OracleError("oracle_collide_sorted returned %d" % rc)
@@ -212,7 +215,7 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
 def collide(cells, species, n_cells, mass, charge, collisions, w, vx, vy, vz, *, dt,
             coulomb_log, seed, step, method=N97, relativistic=False, correction=True,
             sort_by_weight=True, max_passes=1, keep_on_fail=False, f_E=0.05, eps0=1.0,
-            c=math.inf, cell_volume=1.0) -> dict:
+            c=math.inf, cell_volume=1.0, pairing: int = ORDER_N) -> dict:
     """One step on particles in any order; vx, vy, vz updated in place."""
     cells = np.ascontiguousarray(cells, dtype=np.int32)
     species = np.ascontiguousarray(species, dtype=np.int32)
@@ -232,8 +235,8 @@ def collide(cells, species, n_cells, mass, charge, collisions, w, vx, vy, vz, *,
     rc = lib().oracle_collide(
         w.shape[0], _p(cells), _p(species), n_cells, S, _p(mass), _p(charge),
         len(collisions), _p(ca), _p(cb), _p(w), _p(vx), _p(vy), _p(vz), _p(cv), cvs,
-        dt, coulomb_log, seed, step, method, int(relativistic), int(correction),
-        int(sort_by_weight), max_passes, int(keep_on_fail), f_E, eps0, c,
+        dt, coulomb_log, seed, step, method, int(pairing), int(relativistic),
+        int(correction), int(sort_by_weight), max_passes, int(keep_on_fail), f_E, eps0, c,
         _p(counters), _p(diag), _p(ccp))
     if rc != 0:
         raise OracleError("oracle_collide returned %d" % rc)

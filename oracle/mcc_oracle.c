@@ -34,6 +34,13 @@
  *   - Random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
  *     counter = {index, cell, step_lo, step_hi16<<16 | collision<<8 | purpose}.
  *   - Random pairs: each species list is ordered by (Philox word, local index).
+ *   - N x N pairing (Sec. 3.1, optional): every pair of the collision once,
+ *     s of Eq. (sab_weighted) with w_max / dV.  The pairs are taken over the
+ *     shuffled lists in rounds: intra-species, the circle schedule on N
+ *     rounded up to even (round r: (r, pad) and ((r+m) mod R, (r-m) mod R),
+ *     R = rounds), pairs with the pad skipped; inter-species, round r pairs
+ *     list-a entry i with list-b entry (i + r) mod N_max.  Pair index
+ *     r * P + slot (P = half the even N, or N_a).
  *   - Inter-species pair k is (big[k], small[k mod N_min]), written with the
  *     collision's first species first; odd intra-species triple
  *     (L0,L1),(L1,L2),(L2,L0) with s/2, then (L3,L4),(L5,L6),...
@@ -57,6 +64,8 @@
 
 #define ORC_TA77 0
 #define ORC_N97 1
+#define ORC_ORDER_N 0
+#define ORC_NXN 1
 
 #define PURPOSE_PAIR 0
 #define PURPOSE_SHUFFLE0 1 /* + species slot (0: first species, 1: second) */
@@ -299,6 +308,7 @@ typedef struct {
   uint64_t seed, step;
   int32_t method, rel, corr, sortw, max_passes, keep_on_fail;
   double fE;
+  int32_t pairing; /* ORC_ORDER_N or ORC_NXN */
 } cfg_t;
 
 typedef struct {
@@ -663,7 +673,29 @@ static int collide_one(const cfg_t *g, uint32_t cell, int coll, int64_t oa,
   } while (0)
 
   int64_t npairs = 0;
-  if (intra) {
+  if (g->pairing == ORC_NXN) {
+    /* Sec. 3.1: all pairs, each once, s with w_max / dV (N_min = 1) */
+    if (intra) {
+      int32_t np = na + (na & 1), R = np - 1, P = np / 2;
+      for (int32_t r = 0; r < R; ++r)
+        for (int32_t m = 0; m < P; ++m) {
+          int32_t x = m == 0 ? r : (r + m) % R;
+          int32_t y = m == 0 ? np - 1 : (r - m + R) % R;
+          if (x >= na || y >= na) continue; /* the pad of an odd N */
+          SCATTER((int64_t)r * P + m, 1.0, 1.0, L[0][x], L[0][y]);
+          ++npairs;
+        }
+    } else {
+      int32_t nmax = na >= nb ? na : nb;
+      for (int32_t r = 0; r < nmax; ++r)
+        for (int32_t i = 0; i < na; ++i) {
+          int32_t j = (i + r) % nmax;
+          if (j >= nb) continue;
+          SCATTER((int64_t)r * na + i, 1.0, 1.0, L[0][i], L[1][j]);
+          ++npairs;
+        }
+    }
+  } else if (intra) {
     /* Sec. 3.2 last paragraphs: N_min = N_alpha - 1; odd N: first three
      * particles paired N x N with s/2. */
     double nmin = (double)(na - 1);
@@ -922,21 +954,22 @@ int oracle_collide_sorted(
     const int32_t *coll_a, const int32_t *coll_b, const double *w, double *vx,
     double *vy, double *vz, const double *cell_volume, double cell_volume_scalar,
     double dt, double coulomb_log, uint64_t seed, uint64_t step, int32_t method,
-    int32_t relativistic, int32_t moment_correction, int32_t sort_by_weight,
-    int32_t max_passes, int32_t keep_on_fail, double f_E, double eps0, double c,
-    const int32_t *cell_list, int32_t n_list, int64_t *counters, double *diag,
-    int32_t *cell_corr_pairs) {
+    int32_t pairing, int32_t relativistic, int32_t moment_correction,
+    int32_t sort_by_weight, int32_t max_passes, int32_t keep_on_fail, double f_E,
+    double eps0, double c, const int32_t *cell_list, int32_t n_list,
+    int64_t *counters, double *diag, int32_t *cell_corr_pairs) {
   int rc = check_common(n, n_cells, n_species, mass, charge, n_coll, coll_a,
                         coll_b, w, dt, coulomb_log, method, relativistic,
                         max_passes, f_E, eps0, c, cell_volume, cell_volume_scalar);
   if (rc) return rc;
+  if (pairing != ORC_ORDER_N && pairing != ORC_NXN) return ORC_ERR_INVALID;
   const int64_t S = n_species;
   if (offsets[0] != 0 || offsets[(int64_t)n_cells * S] != n) return ORC_ERR_INVALID;
   for (int64_t i = 0; i < (int64_t)n_cells * S; ++i)
     if (offsets[i + 1] < offsets[i]) return ORC_ERR_INVALID;
   cfg_t g = {n_species, mass, charge, n_coll, coll_a, coll_b, dt, coulomb_log,
              eps0, c, seed, step, method, relativistic, moment_correction,
-             sort_by_weight, max_passes, keep_on_fail, f_E};
+             sort_by_weight, max_passes, keep_on_fail, f_E, pairing};
   stats_t st;
   memset(&st, 0, sizeof(st));
   int32_t nl = cell_list ? n_list : n_cells;
@@ -982,7 +1015,7 @@ int oracle_collide(int64_t n, const int32_t *cells, const int32_t *species,
                    double *vy, double *vz, const double *cell_volume,
                    double cell_volume_scalar, double dt, double coulomb_log,
                    uint64_t seed, uint64_t step, int32_t method,
-                   int32_t relativistic, int32_t moment_correction,
+                   int32_t pairing, int32_t relativistic, int32_t moment_correction,
                    int32_t sort_by_weight, int32_t max_passes,
                    int32_t keep_on_fail, double f_E, double eps0, double c,
                    int64_t *counters, double *diag, int32_t *cell_corr_pairs) {
@@ -1013,8 +1046,9 @@ int oracle_collide(int64_t n, const int32_t *cells, const int32_t *species,
   int rc = oracle_collide_sorted(
       n, n_cells, n_species, off, mass, charge, n_coll, coll_a, coll_b, gw, gx,
       gy, gz, cell_volume, cell_volume_scalar, dt, coulomb_log, seed, step,
-      method, relativistic, moment_correction, sort_by_weight, max_passes,
-      keep_on_fail, f_E, eps0, c, NULL, 0, counters, diag, cell_corr_pairs);
+      method, pairing, relativistic, moment_correction, sort_by_weight,
+      max_passes, keep_on_fail, f_E, eps0, c, NULL, 0, counters, diag,
+      cell_corr_pairs);
   if (rc == ORC_OK) {
     for (int64_t j = 0; j < n; ++j) {
       vx[perm[j]] = gx[j];
@@ -1093,8 +1127,8 @@ int oracle_collide_sorted_traced(
   int rc = oracle_collide_sorted(
       n, n_cells, n_species, offsets, mass, charge, n_coll, coll_a, coll_b, w,
       vx, vy, vz, NULL, cell_volume_scalar, dt, coulomb_log, seed, step, method,
-      relativistic, 1, sort_by_weight, 1, 0, f_E, 1.0, c, NULL, 0, NULL, NULL,
-      NULL);
+      ORC_ORDER_N, relativistic, 1, sort_by_weight, 1, 0, f_E, 1.0, c, NULL, 0,
+      NULL, NULL, NULL);
   g_trace = NULL;
   return rc;
 }
