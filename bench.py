@@ -14,6 +14,7 @@ line.
   python bench.py --paper-test1            (the paper's Test 1 cases: one JSON line each)
   python bench.py --paper-test2            (the paper's Test 2 cases: one JSON line each)
   python bench.py --paper-test3            (the paper's Test 3 cases: one JSON line each)
+  python bench.py --nxn                    (N x N against order-N pairing, one JSON line each)
 """
 import argparse
 import hashlib
@@ -51,6 +52,9 @@ def parse():
                     help="only time the paper's Test 1 cases (SI units, 180 cells, FP64) and exit")
     ap.add_argument("--paper-test2", action="store_true",
                     help="only time the paper's Test 2 cases (SI units, 180 cells, FP64) and exit")
+    ap.add_argument("--nxn", action="store_true",
+                    help="only time the N x N pairing (Sec. 3.1) against order-N on 1024 cells "
+                         "of 256 electrons + 256 ions, and exit")
     ap.add_argument("--paper-test3", action="store_true",
                     help="only time the paper's Test 3 cases (SI units, 1600 cells, FP64) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -199,10 +203,42 @@ def paper_tests(which, steps, warmup):
         torch.cuda.empty_cache()
 
 
+def nxn_bench(steps, warmup):
+    """N x N pairing against order-N on the same workload (1024 cells of 256
+    electrons + 256 ions, three collisions): step time and binary pair
+    scatters per second."""
+    import torch
+    from paper_2407_19151_amd import native, runner
+    from paper_2407_19151_amd import workloads as W
+    ctx = native.Context(0)
+    wl = W.config5()
+    for pairing, prec in ((1, native.MCC_FP64), (1, native.MCC_FP32_KINEMATICS),
+                          (0, native.MCC_FP64), (0, native.MCC_FP32_KINEMATICS)):
+        dw = runner.DeviceWorkload(wl)
+        plan = runner.make_plan(ctx, dw, params=runner.params_for(wl, pairing=pairing,
+                                                                  precision=prec),
+                                autotune=False)
+        ms, _ = time_plan(plan, steps, warmup, first_step=0)
+        plan.close()
+        runner.collide_sorted(ctx, dw, 0, params=runner.params_for(wl, pairing=pairing,
+                                                                   precision=prec))
+        pairs = native.read_stats(dw.stats)["pairs"]
+        print(json.dumps({"workload": wl.name, "pairing": "nxn" if pairing else "order_n",
+                          "dtype": "f32 kinematics" if prec else "f64", "ms_per_step": ms,
+                          "pairs_per_step": int(pairs),
+                          "pair_scatters_per_s": pairs / (ms * 1e-3), "steps": steps}),
+              flush=True)
+        del dw
+        torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.nxn:
+        nxn_bench(args.steps, args.warmup)
         return
     if args.paper_test1 or args.paper_test2 or args.paper_test3:
         paper_tests(1 if args.paper_test1 else 2 if args.paper_test2 else 3, args.steps, args.warmup)

@@ -55,6 +55,15 @@ typedef enum {
 typedef enum { MCC_TA77 = 0, MCC_N97 = 1 } mcc_method;
 typedef enum { MCC_FP64 = 0, MCC_FP32_KINEMATICS = 1 } mcc_precision;
 typedef enum { MCC_FAIL_RESET = 0, MCC_FAIL_KEEP = 1 } mcc_fail_policy;
+/* Binary pairing of the scatter.  ORDER_N: the TA77 random pairs of Fig. 1
+ * (Sec. 3.2), s of Eq. (sab_TA77) with w_max N_min / dV.  NXN: every pair of
+ * the collision once (Sec. 3.1), s of Eq. (sab_weighted) with w_max / dV and
+ * the same w_min/w_max acceptance; the pairs run in rounds of disjoint pairs
+ * over the shuffled lists (intra-species: the circle schedule on N rounded
+ * up to even, N - 1 or N rounds; inter-species: round r pairs list-a entry i
+ * with list-b entry (i + r) mod N_max, N_max rounds).  O(N^2) pairs per cell;
+ * the momentum restore and energy correction are the same for both. */
+typedef enum { MCC_PAIRING_ORDER_N = 0, MCC_PAIRING_NXN = 1 } mcc_pairing;
 
 #define MCC_MAX_SPECIES 8
 #define MCC_MAX_COLLISIONS 32
@@ -83,6 +92,7 @@ typedef struct {
   int32_t max_passes;        /* passes of the energy-pair loop, >= 1 (default 1) */
   int32_t on_failure;        /* mcc_fail_policy (Sec. 6.2) */
   int32_t diagnostics;       /* 1: measure residual momentum/energy per collision into stats */
+  int32_t pairing;           /* mcc_pairing (default ORDER_N) */
   double f_E;                /* energy-correction factor, 0 < f_E < 1 (Eq. (23); default 0.05) */
   double eps0;               /* vacuum permittivity in the caller's units (default 1) */
   double c;                  /* speed of light (relativistic only) */
@@ -103,7 +113,8 @@ typedef struct mcc_ctx mcc_ctx;
 typedef struct mcc_plan mcc_plan;
 
 /* Defaults: N97, FP64, non-relativistic, correction on, sort on, one pass,
- * reset on failure, no diagnostics, f_E = 0.05, eps0 = 1, c = 0. */
+ * reset on failure, no diagnostics, order-N pairing, f_E = 0.05, eps0 = 1,
+ * c = 0. */
 void mcc_default_params(mcc_params *p);
 
 const char *mcc_status_string(mcc_status s);
@@ -213,7 +224,7 @@ mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells,
  * leaves (vx, vy, vz) unchanged (several tangents of one state); 1 also
  * writes the primal step.  Diagnostics and per-cell counts are not
  * produced; stats (nullable) counts as for mcc_collide_sorted.
- * Errors: MCC_ERR_UNSUPPORTED for the relativistic or FP32 forms;
+ * Errors: MCC_ERR_UNSUPPORTED for the relativistic, FP32 or N x N forms;
  * MCC_ERR_INVALID for a nonzero lnL tangent with lnL <= 0.
  */
 mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells,

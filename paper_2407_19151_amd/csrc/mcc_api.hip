@@ -23,6 +23,9 @@ const void *const *mcc_kernel_table_tan();
 const void *const *mcc_kernel_table_fp64_diag();
 const void *const *mcc_kernel_table_fp32_diag();
 const void *const *mcc_kernel_table_rel_diag();
+const void *const *mcc_kernel_table_fp64_nxn();
+const void *const *mcc_kernel_table_fp32_nxn();
+const void *const *mcc_kernel_table_rel_nxn();
 
 namespace mcc {
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -91,6 +94,9 @@ const void *const *kernel_table(int mode) {
     case MODE_FP64_DIAG: return mcc_kernel_table_fp64_diag();
     case MODE_FP32_DIAG: return mcc_kernel_table_fp32_diag();
     case MODE_REL_DIAG: return mcc_kernel_table_rel_diag();
+    case MODE_FP64_NXN: return mcc_kernel_table_fp64_nxn();
+    case MODE_FP32_NXN: return mcc_kernel_table_fp32_nxn();
+    case MODE_REL_NXN: return mcc_kernel_table_rel_nxn();
     default: return mcc_kernel_table_rel();
   }
 }
@@ -148,6 +154,9 @@ mcc_status from_hip(hipError_t e) {
 // kernel family of a step: precision / physics, and whether diagnostics are
 // measured (A.diag, set by fill_args)
 int mode_of(const mcc_params *p, const CollideArgs &A) {
+  if (p->pairing == MCC_PAIRING_NXN)
+    return p->relativistic ? MODE_REL_NXN
+           : p->precision == MCC_FP32_KINEMATICS ? MODE_FP32_NXN : MODE_FP64_NXN;
   if (p->relativistic) return A.diag ? MODE_REL_DIAG : MODE_REL;
   if (p->precision == MCC_FP32_KINEMATICS) return A.diag ? MODE_FP32_DIAG : MODE_FP32;
   return A.diag ? MODE_FP64_DIAG : MODE_FP64;
@@ -175,6 +184,8 @@ mcc_status check_step(int64_t n, int32_t n_cells, int32_t n_species, const doubl
   if (p->precision != MCC_FP64 && p->precision != MCC_FP32_KINEMATICS) return MCC_ERR_INVALID;
   if (p->on_failure != MCC_FAIL_RESET && p->on_failure != MCC_FAIL_KEEP) return MCC_ERR_INVALID;
   if (p->max_passes < 1) return MCC_ERR_INVALID;
+  if (p->pairing != MCC_PAIRING_ORDER_N && p->pairing != MCC_PAIRING_NXN) return MCC_ERR_INVALID;
+  if (p->pairing == MCC_PAIRING_NXN && p->diagnostics) return MCC_ERR_UNSUPPORTED;
   if (!(p->f_E > 0.0 && p->f_E < 1.0)) return MCC_ERR_INVALID;
   if (!(p->eps0 > 0.0) || !std::isfinite(p->eps0)) return MCC_ERR_INVALID;
   if (p->relativistic && !(p->c > 0.0 && std::isfinite(p->c))) return MCC_ERR_INVALID;
@@ -335,6 +346,7 @@ void mcc_default_params(mcc_params *p) {
   p->max_passes = 1;
   p->on_failure = MCC_FAIL_RESET;
   p->diagnostics = 0;
+  p->pairing = MCC_PAIRING_ORDER_N;
   p->f_E = 0.05;
   p->eps0 = 1.0;
   p->c = 0.0;
@@ -503,7 +515,8 @@ mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells, int3
   if (n > 0 && (!tx || !ty || !tz)) return MCC_ERR_INVALID;
   if (!std::isfinite(coulomb_log_tangent)) return MCC_ERR_INVALID;
   if (coulomb_log_tangent != 0.0 && !(coulomb_log > 0.0)) return MCC_ERR_INVALID;
-  if (p->relativistic || p->precision != MCC_FP64) return MCC_ERR_UNSUPPORTED;
+  if (p->relativistic || p->precision != MCC_FP64 || p->pairing != MCC_PAIRING_ORDER_N)
+    return MCC_ERR_UNSUPPORTED;
   HIP_TRY(hipSetDevice(ctx->device));
   if (!ensure_lists(ctx, ctx->lists, ctx->counts, n_cells)) return MCC_ERR_OOM;
   CollideArgs A;

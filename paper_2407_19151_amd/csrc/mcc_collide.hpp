@@ -554,7 +554,10 @@ __device__ __forceinline__ void for_owned(int n, F &&f) {
 // ---------------------------------------------------------------------------
 // The kernel
 // ---------------------------------------------------------------------------
-template <int TPC, int CAP, typename KR, bool REL, int LAY, bool TAN = false, bool DIAG = false>
+// NXN: every pair once (Sec. 3.1) instead of the order-N random pairs; its
+// own instantiations, so the order-N kernels carry none of its registers
+template <int TPC, int CAP, typename KR, bool REL, int LAY, bool TAN = false, bool DIAG = false,
+          bool NXN = false>
 __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8, TAN))
     collide_kernel(CollideArgs A) {
   constexpr int PPT = CAP / TPC;
@@ -571,8 +574,9 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   // their room would cost a resident cell per CU (read from HBM there)
   constexpr bool W_LDS = LAY != LAYOUT_COMPACT || CAP <= 1024;
   // pairs of intra-species collisions run as one pass (not in the tangent,
-  // relativistic and diagnostic forms)
-  constexpr bool DUAL = !TAN && !REL && !DIAG;
+  // relativistic, diagnostic and N x N forms)
+  constexpr bool DUAL = !TAN && !REL && !DIAG && !NXN;
+  static_assert(!(NXN && (TAN || DIAG)), "N x N pairing has no tangent or diagnostic form");
   static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
   static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT && !DIAG),
                 "the tangent form is FP64 non-relativistic, without diagnostics");
@@ -972,74 +976,126 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       // N_min / dV of each collision of the pass (once per pass, not per chain)
       const double nmin_dv = nmin / dV, nmin_dv_b = (double)(nb - 1) / dV;
       const bool odd = intra && (na & 1);
-      // Pairs that share a particle form a chain, run in order by one lane:
-      // the odd triple (L0,L1),(L1,L2),(L2,L0); in an inter-species collision
-      // the pairs k, k + N_min, k + 2 N_min, ... (they share small[k]).
-      // Different chains touch disjoint particles, so one barrier ends the
-      // scatter and every particle sees its pairs in ascending k.  A dual
-      // pass runs the chains of species b after those of species a.
-      const int ncha = intra ? (odd ? 1 + (na - 3) / 2 : na / 2) : Nmin;
-      const bool oddb = dual && (nb & 1);
-      const int nchb = dual ? (oddb ? 1 + (nb - 3) / 2 : nb / 2) : 0;
-      const uint32_t c3pb = ctr3(step, k + 1, PURPOSE_PAIR);
-      for (int ch0 = t; ch0 < ncha + nchb; ch0 += TPC) {
-        const bool sb = ch0 >= ncha;  // (dual pass) a chain of species b
-        const int ch = sb ? ch0 - ncha : ch0;
-        const bool odds = sb ? oddb : odd;
-        const int len = intra ? ((odds && ch == 0) ? 3 : 1) : (Nmax - ch + Nmin - 1) / Nmin;
-        // the constants of the collision this chain belongs to
-        const CollConst &Cs = s_cc[sb ? 1 : 0];
-        const double nmins_dv = sb ? nmin_dv_b : nmin_dv;
-        const uint32_t c3s = sb ? c3pb : c3p;
-        for (int r = 0; r < len; ++r) {
-          int I, J;
-          uint32_t kp;
-          double f = 1.0;
-          if (intra) {
-            const uint16_t *L = sb ? L1 : L0;
-            if (odds) {
-              if (ch == 0) {
-                I = L[r];
-                J = L[r == 2 ? 0 : r + 1];
-                kp = (uint32_t)r;
-                f = 0.5;
-              } else {
-                const int m = ch - 1;
-                I = L[3 + 2 * m];
-                J = L[4 + 2 * m];
-                kp = (uint32_t)(3 + m);
+      if constexpr (NXN) {
+        // N x N (Sec. 3.1): every pair once with s of Eq. (sab_weighted)
+        // (w_max / dV), in rounds of disjoint pairs, one barrier per round.
+        //  intra: the circle schedule on np = N rounded up to even; round r
+        //         pairs (r, np-1) and ((r+m) mod R, (r-m) mod R), 0 < m <
+        //         np/2, R = np - 1 rounds; pairs that touch the pad are skipped
+        //  inter: round r pairs list-a entry i with list-b entry
+        //         (i + r) mod N_max; N_max rounds of min(N_a, N_b) pairs,
+        //         visited from the shorter list
+        // kp = r * P + slot, P = np / 2 (intra) or N_a (inter).
+        const double cf = C.coef / dV;
+        const int np = na + (na & 1), R = intra ? np - 1 : Nmax;
+        const int P = intra ? np / 2 : na;
+        const int per = intra ? np / 2 : Nmin;  // slots visited per round
+        for (int r = 0; r < R; ++r) {
+          for (int sl = t; sl < per; sl += TPC) {
+            int I = -1, J = -1, i = sl;
+            if (intra) {
+              const int x = sl == 0 ? r : (r + sl) % R;
+              const int y = sl == 0 ? np - 1 : (r - sl + R) % R;
+              if (x < na && y < na) {
+                I = L0[x];
+                J = L0[y];
               }
             } else {
-              I = L[2 * ch];
-              J = L[2 * ch + 1];
-              kp = (uint32_t)ch;
+              // a slot of the shorter list; i indexes list a, j list b
+              i = abig ? (sl - r + Nmax) % Nmax : sl;
+              const int j = abig ? sl : (sl + r) % Nmax;
+              I = L0[i];
+              J = L1[j];
             }
-          } else {
-            const int kk = r * Nmin + ch;
-            I = abig ? L0[kk] : L0[ch];
-            J = abig ? L1[ch] : L1[kk];
-            kp = (uint32_t)kk;
+            if (I < 0) continue;
+            const uint32_t kp = (uint32_t)(r * P + i);
+            if constexpr (REL)
+              scatter_pair_rel(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, ma, mb, A.c, A.method,
+                               (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
+            else if constexpr (sizeof(KR) == 8)
+              scatter_pair_nr_f64(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, C.fa, C.fb, A.method,
+                                  (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
+            else
+              scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, C.fa, C.fb, A.method,
+                                  (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
           }
-          const double cf = Cs.coef * f * nmins_dv;
-          if constexpr (REL)
-            scatter_pair_rel(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, ma, mb, A.c, A.method,
-                             (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
-          else if constexpr (TAN)
-            scatter_pair_nr_tan(M.vx, M.vy, M.vz, M.tx, M.ty, M.tz, M.w, I, J, kp, cf, C.fa, C.fb,
-                                A.method, (uint32_t)cell, step_lo, c3p, k0, k1, A.n97, A.dlnl);
-          else if constexpr (sizeof(KR) == 8)
-            scatter_pair_nr_f64(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, Cs.fa, Cs.fb, A.method,
-                                (uint32_t)cell, step_lo, c3s, k0, k1, A.n97);
-          else
-            scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, Cs.fa, Cs.fb, A.method,
-                                (uint32_t)cell, step_lo, c3s, k0, k1, A.n97);
+          if (r + 1 < R) __syncthreads();
         }
-      }
-      __syncthreads();
-      if (t == 0) {
-        s_st[0] += intra ? (odd ? 3 + (na - 3) / 2 : na / 2) : Nmax;
-        if (dual) s_st[0] += oddb ? 3 + (nb - 3) / 2 : nb / 2;
-        s_st[3] += dual ? 2 : 1;
+        __syncthreads();
+        if (t == 0) {
+          s_st[0] += intra ? (unsigned long long)na * (na - 1) / 2 : (unsigned long long)na * nb;
+          s_st[3] += 1;
+        }
+      } else {
+        // Pairs that share a particle form a chain, run in order by one lane:
+        // the odd triple (L0,L1),(L1,L2),(L2,L0); in an inter-species collision
+        // the pairs k, k + N_min, k + 2 N_min, ... (they share small[k]).
+        // Different chains touch disjoint particles, so one barrier ends the
+        // scatter and every particle sees its pairs in ascending k.  A dual
+        // pass runs the chains of species b after those of species a.
+        const int ncha = intra ? (odd ? 1 + (na - 3) / 2 : na / 2) : Nmin;
+        const bool oddb = dual && (nb & 1);
+        const int nchb = dual ? (oddb ? 1 + (nb - 3) / 2 : nb / 2) : 0;
+        const uint32_t c3pb = ctr3(step, k + 1, PURPOSE_PAIR);
+        for (int ch0 = t; ch0 < ncha + nchb; ch0 += TPC) {
+          const bool sb = ch0 >= ncha;  // (dual pass) a chain of species b
+          const int ch = sb ? ch0 - ncha : ch0;
+          const bool odds = sb ? oddb : odd;
+          const int len = intra ? ((odds && ch == 0) ? 3 : 1) : (Nmax - ch + Nmin - 1) / Nmin;
+          // the constants of the collision this chain belongs to
+          const CollConst &Cs = s_cc[sb ? 1 : 0];
+          const double nmins_dv = sb ? nmin_dv_b : nmin_dv;
+          const uint32_t c3s = sb ? c3pb : c3p;
+          for (int r = 0; r < len; ++r) {
+            int I, J;
+            uint32_t kp;
+            double f = 1.0;
+            if (intra) {
+              const uint16_t *L = sb ? L1 : L0;
+              if (odds) {
+                if (ch == 0) {
+                  I = L[r];
+                  J = L[r == 2 ? 0 : r + 1];
+                  kp = (uint32_t)r;
+                  f = 0.5;
+                } else {
+                  const int m = ch - 1;
+                  I = L[3 + 2 * m];
+                  J = L[4 + 2 * m];
+                  kp = (uint32_t)(3 + m);
+                }
+              } else {
+                I = L[2 * ch];
+                J = L[2 * ch + 1];
+                kp = (uint32_t)ch;
+              }
+            } else {
+              const int kk = r * Nmin + ch;
+              I = abig ? L0[kk] : L0[ch];
+              J = abig ? L1[ch] : L1[kk];
+              kp = (uint32_t)kk;
+            }
+            const double cf = Cs.coef * f * nmins_dv;
+            if constexpr (REL)
+              scatter_pair_rel(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, ma, mb, A.c, A.method,
+                               (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
+            else if constexpr (TAN)
+              scatter_pair_nr_tan(M.vx, M.vy, M.vz, M.tx, M.ty, M.tz, M.w, I, J, kp, cf, C.fa, C.fb,
+                                  A.method, (uint32_t)cell, step_lo, c3p, k0, k1, A.n97, A.dlnl);
+            else if constexpr (sizeof(KR) == 8)
+              scatter_pair_nr_f64(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, Cs.fa, Cs.fb, A.method,
+                                  (uint32_t)cell, step_lo, c3s, k0, k1, A.n97);
+            else
+              scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, Cs.fa, Cs.fb, A.method,
+                                  (uint32_t)cell, step_lo, c3s, k0, k1, A.n97);
+          }
+        }
+        __syncthreads();
+        if (t == 0) {
+          s_st[0] += intra ? (odd ? 3 + (na - 3) / 2 : na / 2) : Nmax;
+          if (dual) s_st[0] += oddb ? 3 + (nb - 3) / 2 : nb / 2;
+          s_st[3] += dual ? 2 : 1;
+        }
       }
 
       MCC_PHASE(3);  // momentum restore and energy sums

@@ -86,9 +86,12 @@ __device__ __forceinline__ double uni(double x) {
 
 // uniform in (0,1), exact in FP64
 __device__ __forceinline__ double unif64(uint32_t a) { return ((double)a + 0.5) * 0x1p-32; }
-// uniform in (0,1), exact in FP32 (top 24 bits of the word)
+// FP32 uniform from the top 23 bits: (2k + 1) 2^-24 is exact in FP32 and
+// lies in [2^-24, 1 - 2^-24], so no word maps to 0 or 1 (a 24-bit form
+// rounds its top value to 1, and N97's inverse CDF would then take log(0)
+// and return a full reversal)
 __device__ __forceinline__ float unif32(uint32_t a) {
-  return ((float)(a >> 8) + 0.5f) * 0x1p-24f;
+  return ((float)(a >> 9) + 0.5f) * 0x1p-23f;
 }
 
 // ---------------------------------------------------------------------------

@@ -17,8 +17,20 @@ enum Mode {
   MODE_FP64_DIAG = 4,
   MODE_FP32_DIAG = 5,
   MODE_REL_DIAG = 6,
-  NMODE = 7
+  // N x N pairing (Sec. 3.1) in the FP64, FP32 and relativistic forms
+  MODE_FP64_NXN = 7,
+  MODE_FP32_NXN = 8,
+  MODE_REL_NXN = 9,
+  NMODE = 10
 };
+
+// the order-N mode whose variants and defaults an N x N mode shares
+inline constexpr int base_mode(int mode) {
+  return mode == MODE_FP64_NXN ? MODE_FP64
+         : mode == MODE_FP32_NXN ? MODE_FP32
+         : mode == MODE_REL_NXN  ? MODE_REL
+                                 : mode;
+}
 
 // layout: 0 all in LDS; 1 compact LDS (weights read from the input);
 // 2 per-workgroup global scratch with one wave per cell
@@ -63,11 +75,12 @@ inline constexpr Variant compact_of(Variant V) {
 }
 
 inline constexpr int default_variant(int mode, int bucket) {
-  return (mode == MODE_FP32 || mode == MODE_FP32_DIAG) ? kDefaultVariantFP32[bucket]
-                                                         : kDefaultVariant[bucket];
+  return (base_mode(mode) == MODE_FP32 || mode == MODE_FP32_DIAG) ? kDefaultVariantFP32[bucket]
+                                                                    : kDefaultVariant[bucket];
 }
 
-inline constexpr Variant variant_of(int mode, int v) {
+inline constexpr Variant variant_of(int m, int v) {
+  const int mode = base_mode(m);
   return ((mode == MODE_REL || mode == MODE_REL_DIAG) && kVariants[v].layout == 1)
              ? kRelVariant4096
          : (mode == MODE_TAN && kVariants[v].cap > 1024 && kVariants[v].layout != 2)

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmcc_hip.so")
 MCC_TA77, MCC_N97 = 0, 1
 MCC_FP64, MCC_FP32_KINEMATICS = 0, 1
 MCC_FAIL_RESET, MCC_FAIL_KEEP = 0, 1
+MCC_PAIRING_ORDER_N, MCC_PAIRING_NXN = 0, 1
 MCC_MAX_SPECIES = 8
 MCC_MAX_COLLISIONS = 32
 MCC_MAX_CELL = 32768
@@ -47,8 +48,8 @@ class mcc_params(C.Structure):
     _fields_ = [("method", C.c_int32), ("precision", C.c_int32), ("relativistic", C.c_int32),
                 ("moment_correction", C.c_int32), ("sort_by_weight", C.c_int32),
                 ("max_passes", C.c_int32), ("on_failure", C.c_int32),
-                ("diagnostics", C.c_int32), ("f_E", C.c_double), ("eps0", C.c_double),
-                ("c", C.c_double)]
+                ("diagnostics", C.c_int32), ("pairing", C.c_int32), ("f_E", C.c_double),
+                ("eps0", C.c_double), ("c", C.c_double)]
 
 
 class mcc_stats(C.Structure):
@@ -134,7 +135,7 @@ def make_params(method: int = MCC_N97, precision: int = MCC_FP64, relativistic: 
                 moment_correction: bool = True, sort_by_weight: bool = True,
                 max_passes: int = 1, on_failure: int = MCC_FAIL_RESET,
                 diagnostics: bool = False, f_E: float = 0.05, eps0: float = 1.0,
-                c: float = 0.0) -> mcc_params:
+                c: float = 0.0, pairing: int = 0) -> mcc_params:
     p = mcc_params()
     load().mcc_default_params(C.byref(p))
     p.method = int(method)
@@ -145,6 +146,7 @@ def make_params(method: int = MCC_N97, precision: int = MCC_FP64, relativistic: 
     p.max_passes = int(max_passes)
     p.on_failure = int(on_failure)
     p.diagnostics = int(bool(diagnostics))
+    p.pairing = int(pairing)
     p.f_E = float(f_E)
     p.eps0 = float(eps0)
     p.c = float(c) if (c is not None and math.isfinite(c)) else 0.0

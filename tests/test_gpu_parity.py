@@ -247,6 +247,50 @@ def test_invalid_offsets_flagged_not_faulting(ctx):
     assert ctx.device_error() == 1
 
 
+def test_fp32_angle_sampler_top_of_the_uniform_range(ctx):
+    """FP32 N97 sampling takes its uniform from the top 23 bits of the word,
+    (k + 1/2) 2^-23, which never rounds to 1: words at the top of the 32-bit
+    range give the far tail of the inverse CDF (1 - cos theta = -ln(1 - u0)
+    / A for large A, at most 16.6 / A), not a reversal.  Top words and
+    random words, s over 12 decades, against the oracle's inverse CDF at the
+    same quantized uniform, to FP32 accuracy."""
+    import torch
+    from paper_2407_19151_amd import native
+    rng = np.random.default_rng(23)
+    top = np.array([2 ** 32 - 1, 2 ** 32 - 2, 2 ** 32 - 64, 2 ** 32 - 128, 2 ** 32 - 129,
+                    2 ** 32 - 256, 2 ** 32 - 300, 2 ** 32 - 4096], dtype=np.uint64)
+    s = np.repeat(10.0 ** np.linspace(-10, 2, 25), top.size)
+    a0 = np.tile(top, 25)
+    s = np.concatenate([s, 10.0 ** rng.uniform(-10, 2, 4000)])
+    a0 = np.concatenate([a0, rng.integers(0, 2 ** 32, 4000, dtype=np.uint64)]).astype(np.uint32)
+    a1 = rng.integers(0, 2 ** 32, s.size, dtype=np.uint64).astype(np.uint32)
+    oc, st, _ = ctx.sample_angles(W.N97, native.MCC_FP32_KINEMATICS, torch.from_numpy(s).cuda(),
+                                  torch.from_numpy(a0.view(np.int32)).cuda(),
+                                  torch.from_numpy(a1.view(np.int32)).cuda())
+    oc, st = oc.cpu().numpy(), st.cpu().numpy()
+    # at the top words 1 + u0 (e^-2A - 1) is about 2^-24 and FP32 keeps only
+    # its leading bits (measured: 7.5e-4 of 1 - cos theta at s = 0.1); the
+    # bar there is 3e-3
+    ntop = 25 * top.size
+    bad = []
+    for i in range(s.size):
+        u0 = (float(int(a0[i]) >> 9) + 0.5) * 2.0 ** -23
+        u1 = (float(int(a1[i]) >> 9) + 0.5) * 2.0 ** -23
+        ro, rs = oracle.sample_angle(W.N97, float(s[i]), u0, u1)
+        if i < ntop:
+            # the change of the unit relative velocity, (st cos phi, st sin phi,
+            # -oc), has length sqrt(2 oc): its error against that length (near
+            # a reversal st comes from the cancellation in 2 - oc)
+            if math.hypot(oc[i] - ro, st[i] - rs) > 3e-3 * math.sqrt(2 * ro) + 1e-30:
+                bad.append((i, s[i], int(a0[i]), oc[i], ro, st[i], rs))
+        elif abs(oc[i] - ro) > 1e-4 * ro + 1e-30 or abs(st[i] - rs) > 1e-4 * max(rs, 1e-3):
+            bad.append((i, s[i], int(a0[i]), oc[i], ro, st[i], rs))
+    assert not bad, bad[:10]
+    # no reversal at small s
+    small = s < 1e-2
+    assert np.all(oc[small] < 0.2)
+
+
 @pytest.mark.parametrize("method", [W.N97, W.TA77])
 def test_device_angle_sampler_matches_oracle_over_s_range(ctx, method):
     """The map s -> (1 - cos theta, sin theta) on the device against the
