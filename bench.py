@@ -282,7 +282,7 @@ def main():
     dom = max(head["bucket_ms"], key=lambda b: head["bucket_ms"][b])
     dom_ms = head["bucket_ms"][dom]
     bd = head["plan"]["buckets"][dom]
-    kname = "collide_kernel<%d, %d, %s, false, %d, false, false>" % (
+    kname = "collide_kernel<%d, %d, %s, false, %d, false, false, false>" % (
         bd["tpc"], bd["cap"], "float" if head_mode == "fp32" else "double", bd["layout"])
     alg_bytes = BYTES_PER_PARTICLE_STEP * per_bucket_n[dom]
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
