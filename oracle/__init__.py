@@ -23,6 +23,7 @@ TA77 = 0
 N97 = 1
 ORDER_N = 0
 NXN = 1
+DUPLICITY = 2
 
 _lib = None
 
@@ -178,7 +179,9 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
                    cell_volume=1.0, cells: Optional[Sequence[int]] = None,
                    n_cells: Optional[int] = None, pairing: int = ORDER_N) -> dict:
     """One step on (cell, species)-grouped arrays; vx, vy, vz updated in place.
-    pairing: ORDER_N (Sec. 3.2) or NXN (every pair once, Sec. 3.1)."""
+    pairing: ORDER_N (Sec. 3.2), NXN (every pair once, Sec. 3.1) or
+    DUPLICITY (order-N pairs, inter-species s with N_max / D, the variant the
+    paper attributes to Higginson et al.)."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     mass = _f64(mass)
     charge = _f64(charge)

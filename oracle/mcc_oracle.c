@@ -41,6 +41,11 @@
  *     R = rounds), pairs with the pad skipped; inter-species, round r pairs
  *     list-a entry i with list-b entry (i + r) mod N_max.  Pair index
  *     r * P + slot (P = half the even N, or N_a).
+ *   - Duplicity pairing (optional; the variant of Higginson et al. that the
+ *     paper describes after Sec. 3.2): the order-N pairs, with an
+ *     inter-species pair's s taken with N_max / D in place of N_min, D the
+ *     number of pairs its fewer-population particle takes in the step.
+ *     Intra-species pairs are unchanged (every particle is paired once).
  *   - Inter-species pair k is (big[k], small[k mod N_min]), written with the
  *     collision's first species first; odd intra-species triple
  *     (L0,L1),(L1,L2),(L2,L0) with s/2, then (L3,L4),(L5,L6),...
@@ -66,6 +71,7 @@
 #define ORC_N97 1
 #define ORC_ORDER_N 0
 #define ORC_NXN 1
+#define ORC_DUPLICITY 2
 
 #define PURPOSE_PAIR 0
 #define PURPOSE_SHUFFLE0 1 /* + species slot (0: first species, 1: second) */
@@ -308,7 +314,7 @@ typedef struct {
   uint64_t seed, step;
   int32_t method, rel, corr, sortw, max_passes, keep_on_fail;
   double fE;
-  int32_t pairing; /* ORC_ORDER_N or ORC_NXN */
+  int32_t pairing; /* ORC_ORDER_N, ORC_NXN or ORC_DUPLICITY */
 } cfg_t;
 
 typedef struct {
@@ -725,7 +731,13 @@ static int collide_one(const cfg_t *g, uint32_t cell, int coll, int64_t oa,
         I = L[0][k % nmn];
         J = L[1][k];
       }
-      SCATTER(k, 1.0, (double)nmn, I, J);
+      double nfac = (double)nmn;
+      if (g->pairing == ORC_DUPLICITY) {
+        /* D: the pairs k' < N_max with k' = k (mod N_min) */
+        int32_t dup = (nmax - k % nmn + nmn - 1) / nmn;
+        nfac = (double)nmax / (double)dup;
+      }
+      SCATTER(k, 1.0, nfac, I, J);
     }
     npairs += nmax;
   }
@@ -962,7 +974,8 @@ int oracle_collide_sorted(
                         coll_b, w, dt, coulomb_log, method, relativistic,
                         max_passes, f_E, eps0, c, cell_volume, cell_volume_scalar);
   if (rc) return rc;
-  if (pairing != ORC_ORDER_N && pairing != ORC_NXN) return ORC_ERR_INVALID;
+  if (pairing != ORC_ORDER_N && pairing != ORC_NXN && pairing != ORC_DUPLICITY)
+    return ORC_ERR_INVALID;
   const int64_t S = n_species;
   if (offsets[0] != 0 || offsets[(int64_t)n_cells * S] != n) return ORC_ERR_INVALID;
   for (int64_t i = 0; i < (int64_t)n_cells * S; ++i)
