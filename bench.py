@@ -204,16 +204,18 @@ def paper_tests(which, steps, warmup):
 
 
 def nxn_bench(steps, warmup):
-    """N x N pairing against order-N on the same workload (1024 cells of 256
-    electrons + 256 ions, three collisions): step time and binary pair
-    scatters per second."""
+    """N x N and duplicity pairing against order-N on the same workload (1024
+    cells of 256 electrons + 256 ions, three collisions): step time and
+    binary pair scatters per second."""
     import torch
     from paper_2407_19151_amd import native, runner
     from paper_2407_19151_amd import workloads as W
     ctx = native.Context(0)
     wl = W.config5()
+    names = {0: "order_n", 1: "nxn", 2: "duplicity"}
     for pairing, prec in ((1, native.MCC_FP64), (1, native.MCC_FP32_KINEMATICS),
-                          (0, native.MCC_FP64), (0, native.MCC_FP32_KINEMATICS)):
+                          (0, native.MCC_FP64), (0, native.MCC_FP32_KINEMATICS),
+                          (2, native.MCC_FP64)):
         dw = runner.DeviceWorkload(wl)
         plan = runner.make_plan(ctx, dw, params=runner.params_for(wl, pairing=pairing,
                                                                   precision=prec),
@@ -223,7 +225,7 @@ def nxn_bench(steps, warmup):
         runner.collide_sorted(ctx, dw, 0, params=runner.params_for(wl, pairing=pairing,
                                                                    precision=prec))
         pairs = native.read_stats(dw.stats)["pairs"]
-        print(json.dumps({"workload": wl.name, "pairing": "nxn" if pairing else "order_n",
+        print(json.dumps({"workload": wl.name, "pairing": names[pairing],
                           "dtype": "f32 kinematics" if prec else "f64", "ms_per_step": ms,
                           "pairs_per_step": int(pairs),
                           "pair_scatters_per_s": pairs / (ms * 1e-3), "steps": steps}),
@@ -282,7 +284,7 @@ def main():
     dom = max(head["bucket_ms"], key=lambda b: head["bucket_ms"][b])
     dom_ms = head["bucket_ms"][dom]
     bd = head["plan"]["buckets"][dom]
-    kname = "collide_kernel<%d, %d, %s, false, %d, false, false, false>" % (
+    kname = "collide_kernel<%d, %d, %s, false, %d, false, false, 0>" % (
         bd["tpc"], bd["cap"], "float" if head_mode == "fp32" else "double", bd["layout"])
     alg_bytes = BYTES_PER_PARTICLE_STEP * per_bucket_n[dom]
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9

@@ -61,9 +61,17 @@ typedef enum { MCC_FAIL_RESET = 0, MCC_FAIL_KEEP = 1 } mcc_fail_policy;
  * the same w_min/w_max acceptance; the pairs run in rounds of disjoint pairs
  * over the shuffled lists (intra-species: the circle schedule on N rounded
  * up to even, N - 1 or N rounds; inter-species: round r pairs list-a entry i
- * with list-b entry (i + r) mod N_max, N_max rounds).  O(N^2) pairs per cell;
- * the momentum restore and energy correction are the same for both. */
-typedef enum { MCC_PAIRING_ORDER_N = 0, MCC_PAIRING_NXN = 1 } mcc_pairing;
+ * with list-b entry (i + r) mod N_max, N_max rounds).  O(N^2) pairs per cell.
+ * DUPLICITY: the order-N pairs with the s of Higginson et al. that the paper
+ * describes after Sec. 3.2: an inter-species pair takes N_max / D in place
+ * of N_min, D the number of pairs its fewer-population particle takes in the
+ * step (intra-species pairs are unchanged).  The momentum restore and energy
+ * correction are the same for all three. */
+typedef enum {
+  MCC_PAIRING_ORDER_N = 0,
+  MCC_PAIRING_NXN = 1,
+  MCC_PAIRING_DUPLICITY = 2
+} mcc_pairing;
 
 #define MCC_MAX_SPECIES 8
 #define MCC_MAX_COLLISIONS 32
@@ -224,7 +232,8 @@ mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells,
  * leaves (vx, vy, vz) unchanged (several tangents of one state); 1 also
  * writes the primal step.  Diagnostics and per-cell counts are not
  * produced; stats (nullable) counts as for mcc_collide_sorted.
- * Errors: MCC_ERR_UNSUPPORTED for the relativistic, FP32 or N x N forms;
+ * Errors: MCC_ERR_UNSUPPORTED for the relativistic or FP32 forms or a pairing
+ * other than ORDER_N;
  * MCC_ERR_INVALID for a nonzero lnL tangent with lnL <= 0.
  */
 mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells,

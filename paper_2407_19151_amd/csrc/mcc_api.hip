@@ -26,6 +26,9 @@ const void *const *mcc_kernel_table_rel_diag();
 const void *const *mcc_kernel_table_fp64_nxn();
 const void *const *mcc_kernel_table_fp32_nxn();
 const void *const *mcc_kernel_table_rel_nxn();
+const void *const *mcc_kernel_table_fp64_dup();
+const void *const *mcc_kernel_table_fp32_dup();
+const void *const *mcc_kernel_table_rel_dup();
 
 namespace mcc {
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
@@ -97,6 +100,9 @@ const void *const *kernel_table(int mode) {
     case MODE_FP64_NXN: return mcc_kernel_table_fp64_nxn();
     case MODE_FP32_NXN: return mcc_kernel_table_fp32_nxn();
     case MODE_REL_NXN: return mcc_kernel_table_rel_nxn();
+    case MODE_FP64_DUP: return mcc_kernel_table_fp64_dup();
+    case MODE_FP32_DUP: return mcc_kernel_table_fp32_dup();
+    case MODE_REL_DUP: return mcc_kernel_table_rel_dup();
     default: return mcc_kernel_table_rel();
   }
 }
@@ -157,6 +163,9 @@ int mode_of(const mcc_params *p, const CollideArgs &A) {
   if (p->pairing == MCC_PAIRING_NXN)
     return p->relativistic ? MODE_REL_NXN
            : p->precision == MCC_FP32_KINEMATICS ? MODE_FP32_NXN : MODE_FP64_NXN;
+  if (p->pairing == MCC_PAIRING_DUPLICITY)
+    return p->relativistic ? MODE_REL_DUP
+           : p->precision == MCC_FP32_KINEMATICS ? MODE_FP32_DUP : MODE_FP64_DUP;
   if (p->relativistic) return A.diag ? MODE_REL_DIAG : MODE_REL;
   if (p->precision == MCC_FP32_KINEMATICS) return A.diag ? MODE_FP32_DIAG : MODE_FP32;
   return A.diag ? MODE_FP64_DIAG : MODE_FP64;
@@ -184,8 +193,10 @@ mcc_status check_step(int64_t n, int32_t n_cells, int32_t n_species, const doubl
   if (p->precision != MCC_FP64 && p->precision != MCC_FP32_KINEMATICS) return MCC_ERR_INVALID;
   if (p->on_failure != MCC_FAIL_RESET && p->on_failure != MCC_FAIL_KEEP) return MCC_ERR_INVALID;
   if (p->max_passes < 1) return MCC_ERR_INVALID;
-  if (p->pairing != MCC_PAIRING_ORDER_N && p->pairing != MCC_PAIRING_NXN) return MCC_ERR_INVALID;
-  if (p->pairing == MCC_PAIRING_NXN && p->diagnostics) return MCC_ERR_UNSUPPORTED;
+  if (p->pairing != MCC_PAIRING_ORDER_N && p->pairing != MCC_PAIRING_NXN &&
+      p->pairing != MCC_PAIRING_DUPLICITY)
+    return MCC_ERR_INVALID;
+  if (p->pairing != MCC_PAIRING_ORDER_N && p->diagnostics) return MCC_ERR_UNSUPPORTED;
   if (!(p->f_E > 0.0 && p->f_E < 1.0)) return MCC_ERR_INVALID;
   if (!(p->eps0 > 0.0) || !std::isfinite(p->eps0)) return MCC_ERR_INVALID;
   if (p->relativistic && !(p->c > 0.0 && std::isfinite(p->c))) return MCC_ERR_INVALID;

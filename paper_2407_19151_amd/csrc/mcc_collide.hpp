@@ -26,6 +26,7 @@ namespace mcc {
 // Where the arrays of a cell live (all cross-thread data is in LDS unless the
 // layout is GLOBAL, whose workgroup is a single wave).
 enum Layout : int { LAYOUT_LDS = 0, LAYOUT_COMPACT = 1, LAYOUT_GLOBAL = 2 };
+enum Pairing : int { PAIR_ORDER_N = 0, PAIR_NXN = 1, PAIR_DUPLICITY = 2 };
 
 struct CellMem {
   double *vx, *vy, *vz;
@@ -554,10 +555,12 @@ __device__ __forceinline__ void for_owned(int n, F &&f) {
 // ---------------------------------------------------------------------------
 // The kernel
 // ---------------------------------------------------------------------------
-// NXN: every pair once (Sec. 3.1) instead of the order-N random pairs; its
-// own instantiations, so the order-N kernels carry none of its registers
+// PAIRING: PAIR_ORDER_N, PAIR_NXN (every pair once, Sec. 3.1) or
+// PAIR_DUPLICITY (the order-N pairs with Higginson et al.'s duplicity s);
+// the other pairings have their own instantiations, so the order-N kernels
+// carry none of their registers
 template <int TPC, int CAP, typename KR, bool REL, int LAY, bool TAN = false, bool DIAG = false,
-          bool NXN = false>
+          int PAIRING = PAIR_ORDER_N>
 __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8, TAN))
     collide_kernel(CollideArgs A) {
   constexpr int PPT = CAP / TPC;
@@ -575,8 +578,11 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   constexpr bool W_LDS = LAY != LAYOUT_COMPACT || CAP <= 1024;
   // pairs of intra-species collisions run as one pass (not in the tangent,
   // relativistic, diagnostic and N x N forms)
-  constexpr bool DUAL = !TAN && !REL && !DIAG && !NXN;
-  static_assert(!(NXN && (TAN || DIAG)), "N x N pairing has no tangent or diagnostic form");
+  constexpr bool NXN = PAIRING == PAIR_NXN;
+  constexpr bool DUP = PAIRING == PAIR_DUPLICITY;
+  constexpr bool DUAL = !TAN && !REL && !DIAG && PAIRING == PAIR_ORDER_N;
+  static_assert(PAIRING == PAIR_ORDER_N || !(TAN || DIAG),
+                "the N x N and duplicity pairings have no tangent or diagnostic form");
   static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
   static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT && !DIAG),
                 "the tangent form is FP64 non-relativistic, without diagnostics");
@@ -1075,7 +1081,12 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
               J = abig ? L1[ch] : L1[kk];
               kp = (uint32_t)kk;
             }
-            const double cf = Cs.coef * f * nmins_dv;
+            double cf = Cs.coef * f * nmins_dv;
+            if constexpr (DUP) {
+              // duplicity s: N_max / D for N_min, D = this chain's length
+              // (the pairs of its fewer-population particle)
+              if (!intra) cf = Cs.coef * ((double)Nmax / dV) / (double)len;
+            }
             if constexpr (REL)
               scatter_pair_rel(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, ma, mb, A.c, A.method,
                                (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);

@@ -1,0 +1,15 @@
+// Instantiations of the collide kernel with duplicity pairing (Higginson et al.'s s), FP32-kinematics form.
+#include "mcc_collide.hpp"
+#include "mcc_variants.hpp"
+
+namespace mcc {
+#define V(i)                                                                     \
+  ((const void *)&collide_kernel<variant_of(MODE_FP32_DUP, i).tpc,             \
+                                 variant_of(MODE_FP32_DUP, i).cap, float, false, \
+                                 variant_of(MODE_FP32_DUP, i).layout, false, false, PAIR_DUPLICITY>)
+const void *const kTable_FP32_DUP[NVARIANT] = {V(0), V(1), V(2),  V(3),  V(4),  V(5),  V(6),
+                                             V(7), V(8), V(9), V(10), V(11), V(12), V(13)};
+#undef V
+}  // namespace mcc
+
+const void *const *mcc_kernel_table_fp32_dup() { return mcc::kTable_FP32_DUP; }

@@ -1,0 +1,15 @@
+// Instantiations of the collide kernel with duplicity pairing (Higginson et al.'s s), FP64 form.
+#include "mcc_collide.hpp"
+#include "mcc_variants.hpp"
+
+namespace mcc {
+#define V(i)                                                                     \
+  ((const void *)&collide_kernel<variant_of(MODE_FP64_DUP, i).tpc,             \
+                                 variant_of(MODE_FP64_DUP, i).cap, double, false, \
+                                 variant_of(MODE_FP64_DUP, i).layout, false, false, PAIR_DUPLICITY>)
+const void *const kTable_FP64_DUP[NVARIANT] = {V(0), V(1), V(2),  V(3),  V(4),  V(5),  V(6),
+                                             V(7), V(8), V(9), V(10), V(11), V(12), V(13)};
+#undef V
+}  // namespace mcc
+
+const void *const *mcc_kernel_table_fp64_dup() { return mcc::kTable_FP64_DUP; }

@@ -4,9 +4,9 @@
 
 namespace mcc {
 #define V(i)                                                                     \
-  ((const void *)&collide_kernel<variant_of(MODE_REL_NXN, i).tpc,                \
+  ((const void *)&collide_kernel<variant_of(MODE_REL_NXN, i).tpc,             \
                                  variant_of(MODE_REL_NXN, i).cap, double, true, \
-                                 variant_of(MODE_REL_NXN, i).layout, false, false, true>)
+                                 variant_of(MODE_REL_NXN, i).layout, false, false, PAIR_NXN>)
 const void *const kTable_REL_NXN[NVARIANT] = {V(0), V(1), V(2),  V(3),  V(4),  V(5),  V(6),
                                              V(7), V(8), V(9), V(10), V(11), V(12), V(13)};
 #undef V

@@ -21,15 +21,19 @@ enum Mode {
   MODE_FP64_NXN = 7,
   MODE_FP32_NXN = 8,
   MODE_REL_NXN = 9,
-  NMODE = 10
+  // duplicity pairing (Higginson et al.'s s) in the same three forms
+  MODE_FP64_DUP = 10,
+  MODE_FP32_DUP = 11,
+  MODE_REL_DUP = 12,
+  NMODE = 13
 };
 
-// the order-N mode whose variants and defaults an N x N mode shares
+// the order-N mode whose variants and defaults another pairing's mode shares
 inline constexpr int base_mode(int mode) {
-  return mode == MODE_FP64_NXN ? MODE_FP64
-         : mode == MODE_FP32_NXN ? MODE_FP32
-         : mode == MODE_REL_NXN  ? MODE_REL
-                                 : mode;
+  return (mode == MODE_FP64_NXN || mode == MODE_FP64_DUP)   ? MODE_FP64
+         : (mode == MODE_FP32_NXN || mode == MODE_FP32_DUP) ? MODE_FP32
+         : (mode == MODE_REL_NXN || mode == MODE_REL_DUP)   ? MODE_REL
+                                                             : mode;
 }
 
 // layout: 0 all in LDS; 1 compact LDS (weights read from the input);

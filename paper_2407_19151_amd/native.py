@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmcc_hip.so")
 MCC_TA77, MCC_N97 = 0, 1
 MCC_FP64, MCC_FP32_KINEMATICS = 0, 1
 MCC_FAIL_RESET, MCC_FAIL_KEEP = 0, 1
-MCC_PAIRING_ORDER_N, MCC_PAIRING_NXN = 0, 1
+MCC_PAIRING_ORDER_N, MCC_PAIRING_NXN, MCC_PAIRING_DUPLICITY = 0, 1, 2
 MCC_MAX_SPECIES = 8
 MCC_MAX_COLLISIONS = 32
 MCC_MAX_CELL = 32768

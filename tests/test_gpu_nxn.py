@@ -171,7 +171,11 @@ def test_nxn_unsupported_forms(ctx):
         runner.collide_sorted_jvp(ctx, dw, tan, 0, params=runner.params_for(wl, pairing=NXN))
     assert e.value.code == -4
     with pytest.raises(native.MCCError) as e:
-        runner.collide_sorted(ctx, dw, 0, params=runner.params_for(wl, pairing=2))
+        runner.collide_sorted(ctx, dw, 0, params=runner.params_for(wl, pairing=2,
+                                                                    diagnostics=True))
+    assert e.value.code == -4
+    with pytest.raises(native.MCCError) as e:
+        runner.collide_sorted(ctx, dw, 0, params=runner.params_for(wl, pairing=3))
     assert e.value.code == -1
 
 
