@@ -15,6 +15,7 @@ line.
   python bench.py --paper-test2            (the paper's Test 2 cases: one JSON line each)
   python bench.py --paper-test3            (the paper's Test 3 cases: one JSON line each)
   python bench.py --nxn                    (N x N against order-N pairing, one JSON line each)
+  python bench.py --rebin                  (incremental re-binning after a push, one JSON line each)
 """
 import argparse
 import hashlib
@@ -52,6 +53,9 @@ def parse():
                     help="only time the paper's Test 1 cases (SI units, 180 cells, FP64) and exit")
     ap.add_argument("--paper-test2", action="store_true",
                     help="only time the paper's Test 2 cases (SI units, 180 cells, FP64) and exit")
+    ap.add_argument("--rebin", action="store_true",
+                    help="only time incremental re-binning (mcc_rebin) against binning from "
+                         "scratch on the 65,536-cell population after a push, and exit")
     ap.add_argument("--nxn", action="store_true",
                     help="only time the N x N pairing (Sec. 3.1) against order-N on 1024 cells "
                          "of 256 electrons + 256 ions, and exit")
@@ -234,6 +238,64 @@ def nxn_bench(steps, warmup):
         torch.cuda.empty_cache()
 
 
+def rebin_bench(steps, warmup):
+    """mcc_rebin on the 65,536-cell population after a push that moves a
+    fraction of the particles to a neighbouring cell (10 % of those jump
+    anywhere), against mcc_bin on the same new keys.  Roofline: the
+    operation's least HBM traffic, 4 B of new cell id read and 4 B of
+    permutation written per particle, plus 64 B when w, vx, vy, vz are moved
+    (read and written once)."""
+    import numpy as np
+    import torch
+    from paper_2407_19151_amd import native
+    from paper_2407_19151_amd import workloads as W
+    ctx = native.Context(0)
+    wl = W.config3()
+    n = wl.n
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    off = dev(wl.offsets)
+    sp = dev(wl.species.astype(np.int32))
+    pay = [dev(a) for a in (wl.w, wl.vx, wl.vy, wl.vz)]
+    rng = np.random.default_rng(5)
+    cell = wl.cells.astype(np.int32)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = events()
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    for frac in (0.01, 0.05):
+        new = cell.copy()
+        mv = rng.uniform(size=n) < frac
+        step = np.where(rng.uniform(size=n) < 0.5, -1, 1)
+        new[mv] = (cell[mv] + step[mv]) % wl.n_cells
+        far = mv & (rng.uniform(size=n) < 0.1)
+        new[far] = rng.integers(0, wl.n_cells, size=int(far.sum()))
+        cn = dev(new.astype(np.int32))
+        t_keys = timed(lambda: ctx.rebin(off, cn, wl.n_cells, wl.n_species))
+        t_pay = timed(lambda: ctx.rebin(off, cn, wl.n_cells, wl.n_species, *pay))
+        t_bin = timed(lambda: ctx.bin(cn, sp, wl.n_cells, wl.n_species))
+        assert ctx.device_error() == 0
+        print(json.dumps({
+            "workload": "65536-cell population (%d particles), %.0f %% moved" % (n, 100 * frac),
+            "rebin_ms": t_keys, "rebin_with_payload_ms": t_pay, "bin_from_scratch_ms": t_bin,
+            "speedup_vs_bin": t_bin / t_keys,
+            "roofline": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0,
+                         "keys": {"bytes_per_particle": 8, "achieved": 8 * n / t_keys / 1e6,
+                                  "frac": 8 * n / t_keys / 1e6 / 8000.0},
+                         "with_payload": {"bytes_per_particle": 72,
+                                          "achieved": 72 * n / t_pay / 1e6,
+                                          "frac": 72 * n / t_pay / 1e6 / 8000.0}},
+            "steps": steps}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -241,6 +303,9 @@ def main():
         return
     if args.nxn:
         nxn_bench(args.steps, args.warmup)
+        return
+    if args.rebin:
+        rebin_bench(args.steps, args.warmup)
         return
     if args.paper_test1 or args.paper_test2 or args.paper_test3:
         paper_tests(1 if args.paper_test1 else 2 if args.paper_test2 else 3, args.steps, args.warmup)

@@ -142,7 +142,8 @@ void mcc_destroy(mcc_ctx *ctx);
 /* Synchronize the context's stream and return the first device-side data
  * error code latched since the last call (0 if none), then clear it.
  * Codes: 1 offsets not monotone or out of [0, n]; 2 cell larger than
- * MCC_MAX_CELL; 3 cell or species id out of range (unsorted entry). */
+ * MCC_MAX_CELL; 3 cell or species id out of range (unsorted entry,
+ * re-binning). */
 mcc_status mcc_device_error(mcc_ctx *ctx, int32_t *code);
 
 /*
@@ -257,6 +258,35 @@ mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells,
 mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells,
                    const int32_t *species_id, int32_t n_cells,
                    int32_t n_species, int64_t *offsets_out, int32_t *perm_out);
+
+/*
+ * Incremental re-binning: the regrouping of a grouped population after its
+ * particles moved to new cells (a particle push between collision steps).
+ * The grouping by cell is the one every collision step starts from (the
+ * particles of a cell, Sec. 2); when few particles change cell, it is
+ * updated in a few streaming passes instead of being rebuilt.
+ *  offsets      device int64[n_cells*n_species + 1]: the current grouping
+ *               (offsets[0] = 0, monotone, offsets[end] = n)
+ *  cells_new    device int32[n]: the new cell of the particle at each
+ *               grouped position (its species does not change)
+ *  offsets_out  device int64[n_cells*n_species + 1]
+ *  perm_out     device int32[n]: perm_out[j] = current position of the
+ *               particle that goes to position j; ascending inside every
+ *               new group, i.e. what mcc_bin returns for cells_new and the
+ *               species of each position
+ *  weights, vx, vy, vz  device double[n], all or none (NULL): permuted in
+ *               place to the new order
+ * Cost: streaming passes over the particles, plus sum over groups of the
+ * square of the particles arriving in that group (each group's arrival list
+ * is sorted in one thread): meant for partial moves; rebuild a wholesale
+ * reshuffle with mcc_bin.  Data errors (cell id out of range, inconsistent
+ * offsets) are latched as for the collide calls; such a particle keeps its
+ * cell.  Errors: MCC_ERR_INVALID for bad arguments (some payload pointers
+ * only), MCC_ERR_UNSUPPORTED above 2^31 - 1 particles or groups.
+ */
+mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                     const int64_t *offsets, const int32_t *cells_new, int64_t *offsets_out,
+                     int32_t *perm_out, double *weights, double *vx, double *vy, double *vz);
 
 /*
  * Batched form: a plan binds the sorted arrays of one particle population

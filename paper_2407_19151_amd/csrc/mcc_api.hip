@@ -49,6 +49,12 @@ hipError_t launch_sample_angles(int method, int precision, int64_t n, const doub
                                 const uint32_t *a0, const uint32_t *a1, double *oc, double *st,
                                 double *A, const double2 *tab, hipStream_t st_);
 hipError_t launch_n97_table(double2 *tab, hipStream_t s);
+hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
+                        const int32_t *cells_new, int64_t *off_new, int32_t *perm,
+                        int32_t *gold, int32_t *gnew, int32_t *alist, uint32_t *flag,
+                        int64_t *mpre, uint32_t *leave, uint32_t *arrive, uint32_t *acur,
+                        uint32_t *cnt, int64_t *aoff, int64_t *tiles, int32_t *err,
+                        hipStream_t s);
 hipError_t launch_gather(int64_t n, const int32_t *perm, const double *w, const double *vx,
                          const double *vy, const double *vz, double *gw, double *gx, double *gy,
                          double *gz, hipStream_t s);
@@ -123,6 +129,9 @@ struct mcc_ctx {
   DevBuf work;
   // unsorted entry
   DevBuf ucnt, tiles, off, cursor, perm, biglist, bigcount, canon, gw, gx, gy, gz;
+  // incremental re-binning
+  DevBuf rb_gold, rb_gnew, rb_alist, rb_flag, rb_mpre, rb_leave, rb_arrive, rb_acur, rb_cnt,
+      rb_aoff;
   int grid[NMODE][NVARIANT] = {};
   int variant[NBUCKET] = {};
 };
@@ -441,7 +450,9 @@ void mcc_destroy(mcc_ctx *ctx) {
   for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->big4k, &ctx->big32k, &ctx->ucnt, &ctx->tiles,
                     &ctx->off, &ctx->cursor, &ctx->perm, &ctx->biglist, &ctx->bigcount,
                     &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97,
-                    &ctx->work})
+                    &ctx->work, &ctx->rb_gold, &ctx->rb_gnew, &ctx->rb_alist, &ctx->rb_flag,
+                    &ctx->rb_mpre, &ctx->rb_leave, &ctx->rb_arrive, &ctx->rb_acur,
+                    &ctx->rb_cnt, &ctx->rb_aoff})
     b->release();
   if (ctx->err) (void)hipFree(ctx->err);
   delete ctx;
@@ -580,6 +591,55 @@ mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int32_t 
   HIP_TRY(hipSetDevice(ctx->device));
   mcc_status st = bin_into(ctx, n, cells, species_id, n_cells, n_species, offsets_out, perm_out);
   if (st != MCC_OK) return st;
+  return finish(ctx);
+}
+
+mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                     const int64_t *offsets, const int32_t *cells_new, int64_t *offsets_out,
+                     int32_t *perm_out, double *weights, double *vx, double *vy, double *vz) {
+  if (!ctx || n < 0 || n_cells < 0 || n_species < 1 || n_species > MCC_MAX_SPECIES ||
+      !offsets || !offsets_out || (n > 0 && (!cells_new || !perm_out)))
+    return MCC_ERR_INVALID;
+  const int any = (weights != nullptr) + (vx != nullptr) + (vy != nullptr) + (vz != nullptr);
+  if (any != 0 && any != 4) return MCC_ERR_INVALID;
+  const int64_t m = (int64_t)n_cells * n_species;
+  if (n > (int64_t)INT32_MAX || m > (int64_t)INT32_MAX) return MCC_ERR_UNSUPPORTED;
+  if (m == 0 && n > 0) return MCC_ERR_INVALID;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const size_t nn = (size_t)std::max<int64_t>(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
+  if (!ctx->rb_gold.ensure(sizeof(int32_t) * nn) || !ctx->rb_gnew.ensure(sizeof(int32_t) * nn) ||
+      !ctx->rb_alist.ensure(sizeof(int32_t) * nn) || !ctx->rb_flag.ensure(sizeof(uint32_t) * nn) ||
+      !ctx->rb_mpre.ensure(sizeof(int64_t) * (nn + 1)) ||
+      !ctx->rb_leave.ensure(sizeof(uint32_t) * mm) ||
+      !ctx->rb_arrive.ensure(sizeof(uint32_t) * mm) ||
+      !ctx->rb_acur.ensure(sizeof(uint32_t) * mm) || !ctx->rb_cnt.ensure(sizeof(uint32_t) * mm) ||
+      !ctx->rb_aoff.ensure(sizeof(int64_t) * (mm + 1)) ||
+      !ctx->tiles.ensure(sizeof(int64_t) * (size_t)scan_tiles_needed(std::max<int64_t>(n, m))))
+    return MCC_ERR_OOM;
+  if (m == 0) {
+    HIP_TRY(launch_set_u64(reinterpret_cast<uint64_t *>(offsets_out), 0ull, ctx->stream));
+    return finish(ctx);
+  }
+  HIP_TRY(launch_rebin(n, m, n_species, n_cells, offsets, cells_new, offsets_out, perm_out,
+                       ctx->rb_gold.as<int32_t>(), ctx->rb_gnew.as<int32_t>(),
+                       ctx->rb_alist.as<int32_t>(), ctx->rb_flag.as<uint32_t>(),
+                       ctx->rb_mpre.as<int64_t>(), ctx->rb_leave.as<uint32_t>(),
+                       ctx->rb_arrive.as<uint32_t>(), ctx->rb_acur.as<uint32_t>(),
+                       ctx->rb_cnt.as<uint32_t>(), ctx->rb_aoff.as<int64_t>(),
+                       ctx->tiles.as<int64_t>(), ctx->err, ctx->stream));
+  if (any && n > 0) {
+    if (!ctx->gw.ensure(sizeof(double) * nn) || !ctx->gx.ensure(sizeof(double) * nn) ||
+        !ctx->gy.ensure(sizeof(double) * nn) || !ctx->gz.ensure(sizeof(double) * nn))
+      return MCC_ERR_OOM;
+    HIP_TRY(launch_gather(n, perm_out, weights, vx, vy, vz, ctx->gw.as<double>(),
+                          ctx->gx.as<double>(), ctx->gy.as<double>(), ctx->gz.as<double>(),
+                          ctx->stream));
+    const size_t b = sizeof(double) * (size_t)n;
+    HIP_TRY(hipMemcpyAsync(weights, ctx->gw.p, b, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(vx, ctx->gx.p, b, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(vy, ctx->gy.p, b, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(vz, ctx->gz.p, b, hipMemcpyDeviceToDevice, ctx->stream));
+  }
   return finish(ctx);
 }
 

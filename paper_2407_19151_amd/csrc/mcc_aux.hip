@@ -122,25 +122,36 @@ __global__ void k_scan_tile_sums(int64_t *tile_sums, int64_t ntiles) {
   }
 }
 
+// a tile's prefix sums: each thread sums its SCAN_PPT consecutive entries,
+// the thread sums are scanned in LDS (log2 SCAN_TPB doubling steps), and
+// each thread writes its entries' offsets
 __global__ void k_scan_apply(const uint32_t *in, int64_t m, const int64_t *tile_off,
                              int64_t *out) {
-  __shared__ int64_t vals[SCAN_TILE];
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
-  for (int j = threadIdx.x; j < SCAN_TILE; j += SCAN_TPB)
-    vals[j] = base + j < m ? (int64_t)in[base + j] : 0;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = tile_off[blockIdx.x];
-    for (int j = 0; j < SCAN_TILE; ++j) {
-      const int64_t x = vals[j];
-      vals[j] = run;
-      run += x;
-    }
-    if (base + SCAN_TILE >= m) out[m] = run;  // last tile writes the total
+  __shared__ int64_t part[SCAN_TPB];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)t * SCAN_PPT;
+  uint32_t v[SCAN_PPT];
+  int64_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < SCAN_PPT; ++j) {
+    v[j] = base + j < m ? in[base + j] : 0u;
+    sum += v[j];
   }
+  part[t] = sum;
   __syncthreads();
-  for (int j = threadIdx.x; j < SCAN_TILE; j += SCAN_TPB)
-    if (base + j < m) out[base + j] = vals[j];
+  for (int d = 1; d < SCAN_TPB; d <<= 1) {
+    const int64_t x = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += x;
+    __syncthreads();
+  }
+  int64_t run = tile_off[blockIdx.x] + part[t] - sum;
+#pragma unroll
+  for (int j = 0; j < SCAN_PPT; ++j) {
+    if (base + j < m) out[base + j] = run;
+    run += v[j];
+  }
+  if (base <= m - 1 && m - 1 < base + SCAN_PPT) out[m] = run;  // the total
 }
 
 // unstable placement of original indices; cursor starts as a copy of offsets
