@@ -14,6 +14,7 @@ line.
   python bench.py --paper-test1            (the paper's Test 1 cases: one JSON line each)
   python bench.py --paper-test2            (the paper's Test 2 cases: one JSON line each)
   python bench.py --paper-test3            (the paper's Test 3 cases: one JSON line each)
+  python bench.py --paper-test3-curve      (T3b and T3c relaxed to equilibrium, sampled)
   python bench.py --nxn                    (N x N against order-N pairing, one JSON line each)
   python bench.py --rebin                  (incremental re-binning after a push, one JSON line each)
 """
@@ -59,6 +60,9 @@ def parse():
     ap.add_argument("--nxn", action="store_true",
                     help="only time the N x N pairing (Sec. 3.1) against order-N on 1024 cells "
                          "of 256 electrons + 256 ions, and exit")
+    ap.add_argument("--paper-test3-curve", action="store_true",
+                    help="relax the paper's T3b and T3c to equilibrium (1.1e6 steps each), "
+                         "sampling T_e and T_i, and exit")
     ap.add_argument("--paper-test3", action="store_true",
                     help="only time the paper's Test 3 cases (SI units, 1600 cells, FP64) and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -296,10 +300,52 @@ def rebin_bench(steps, warmup):
             "steps": steps}), flush=True)
 
 
+def paper_test3_curve(total=1_100_000, every=50_000):
+    """T3b and T3c (N_e = N_i = 512, w_e = 6 w_i, without and with the
+    correction) stepped to equilibrium; one JSON line per sample with the
+    species temperatures and the momentum and energy drift."""
+    import numpy as np
+    import torch
+    from paper_2407_19151_amd import native, runner
+    from paper_2407_19151_amd import workloads as W
+    ctx = native.Context(0)
+    for case in ("T3c", "T3b"):
+        wl = W.paper_test3(case)
+        corr = int(wl.extra["moment_correction"])
+        m = wl.mass[wl.species] * wl.w
+        v0 = wl.velocities()
+        p0 = (m * v0).sum(1)
+        e0 = (0.5 * m * (v0 * v0).sum(0)).sum()
+        ps = (m * np.linalg.norm(v0, axis=0)).sum()
+        dw = runner.DeviceWorkload(wl)
+        plan = runner.make_plan(ctx, dw, params=runner.params_for(wl, moment_correction=corr),
+                                autotune=False)
+        te, ti = W.species_temperatures(wl, v0)
+        print(json.dumps({"case": case, "step": 0, "t_fs": 0.0, "T_e": te, "T_i": ti}),
+              flush=True)
+        t0 = time.perf_counter()
+        for k in range(every, total + 1, every):
+            plan.run(k - every, every)
+            torch.cuda.synchronize()
+            v = dw.velocities()
+            te, ti = W.species_temperatures(wl, v)
+            print(json.dumps({"case": case, "step": k, "t_fs": k * wl.dt * 1e15, "T_e": te,
+                              "T_i": ti,
+                              "rel_dP": float(np.abs((m * v).sum(1) - p0).max() / ps),
+                              "rel_dE": float(abs((0.5 * m * (v * v).sum(0)).sum() - e0) / e0),
+                              "wall_s": time.perf_counter() - t0}), flush=True)
+        plan.close()
+        del dw
+        torch.cuda.empty_cache()
+
+
 def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.paper_test3_curve:
+        paper_test3_curve()
         return
     if args.nxn:
         nxn_bench(args.steps, args.warmup)
