@@ -94,6 +94,33 @@ def test_parity_large_global_scratch_cells(ctx):
     _parity(ctx, wl, 2)
 
 
+def test_parity_at_the_maximum_cell_and_one_past_it(ctx):
+    """A cell of exactly MCC_MAX_CELL particles is stepped like any other; a
+    cell one particle larger is skipped (left unchanged) and reported as code
+    2, while the cells around it are still stepped."""
+    from paper_2407_19151_amd import native
+    sizes = [(16384, 16384), (50, 30)]
+    wl = custom_workload(sizes, seed=47)
+    _parity(ctx, wl, 1)
+    over = custom_workload([(40, 20), (16385, 16384), (70, 35)], seed=48)
+    v0 = over.velocities().copy()
+    vg, _, _ = _gpu_step_unchecked(ctx, over, 2)
+    assert ctx.device_error() == 2
+    big = over.cells == 1
+    assert np.array_equal(vg[:, big], v0[:, big])
+    ref = over.copy()
+    oracle_step(ref, 2, cells=[0, 2])
+    info = check_parity(over, vg, ref.velocities(), v0)
+    print("  cells around the over-size one: %s" % info, flush=True)
+
+
+def _gpu_step_unchecked(ctx, wl, step, **pover):
+    from paper_2407_19151_amd import native, runner
+    dw = runner.DeviceWorkload(wl)
+    runner.collide_sorted(ctx, dw, step, params=runner.params_for(wl, **pover))
+    return dw.velocities(), native.read_stats(dw.stats), dw.cell_corr.cpu().numpy()
+
+
 @pytest.mark.parametrize("wmode", ["lognormal", "two", "clustered", "equal"])
 def test_parity_weight_orders(ctx, wmode):
     """Distinct weights (bucket order), two weight classes (crowded bucket:
