@@ -53,7 +53,7 @@ hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const 
                         const int32_t *cells_new, int64_t *off_new, int32_t *perm,
                         int32_t *gold, int32_t *gnew, int32_t *alist, uint32_t *flag,
                         int64_t *mpre, uint32_t *leave, uint32_t *arrive, uint32_t *acur,
-                        uint32_t *cnt, int64_t *aoff, int64_t *tiles, int32_t *err,
+                        uint32_t *cnt, int64_t *aoff, void *rec, int64_t *tiles, int32_t *err,
                         hipStream_t s);
 hipError_t launch_gather(int64_t n, const int32_t *perm, const double *w, const double *vx,
                          const double *vy, const double *vz, double *gw, double *gx, double *gy,
@@ -131,7 +131,7 @@ struct mcc_ctx {
   DevBuf ucnt, tiles, off, cursor, perm, biglist, bigcount, canon, gw, gx, gy, gz;
   // incremental re-binning
   DevBuf rb_gold, rb_gnew, rb_alist, rb_flag, rb_mpre, rb_leave, rb_arrive, rb_acur, rb_cnt,
-      rb_aoff;
+      rb_aoff, rb_rec;
   int grid[NMODE][NVARIANT] = {};
   int variant[NBUCKET] = {};
 };
@@ -452,7 +452,7 @@ void mcc_destroy(mcc_ctx *ctx) {
                     &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97,
                     &ctx->work, &ctx->rb_gold, &ctx->rb_gnew, &ctx->rb_alist, &ctx->rb_flag,
                     &ctx->rb_mpre, &ctx->rb_leave, &ctx->rb_arrive, &ctx->rb_acur,
-                    &ctx->rb_cnt, &ctx->rb_aoff})
+                    &ctx->rb_cnt, &ctx->rb_aoff, &ctx->rb_rec})
     b->release();
   if (ctx->err) (void)hipFree(ctx->err);
   delete ctx;
@@ -614,6 +614,7 @@ mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species
       !ctx->rb_arrive.ensure(sizeof(uint32_t) * mm) ||
       !ctx->rb_acur.ensure(sizeof(uint32_t) * mm) || !ctx->rb_cnt.ensure(sizeof(uint32_t) * mm) ||
       !ctx->rb_aoff.ensure(sizeof(int64_t) * (mm + 1)) ||
+      !ctx->rb_rec.ensure(48 * mm) ||
       !ctx->tiles.ensure(sizeof(int64_t) * (size_t)scan_tiles_needed(std::max<int64_t>(n, m))))
     return MCC_ERR_OOM;
   if (m == 0) {
@@ -625,7 +626,7 @@ mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species
                        ctx->rb_alist.as<int32_t>(), ctx->rb_flag.as<uint32_t>(),
                        ctx->rb_mpre.as<int64_t>(), ctx->rb_leave.as<uint32_t>(),
                        ctx->rb_arrive.as<uint32_t>(), ctx->rb_acur.as<uint32_t>(),
-                       ctx->rb_cnt.as<uint32_t>(), ctx->rb_aoff.as<int64_t>(),
+                       ctx->rb_cnt.as<uint32_t>(), ctx->rb_aoff.as<int64_t>(), ctx->rb_rec.p,
                        ctx->tiles.as<int64_t>(), ctx->err, ctx->stream));
   if (any && n > 0) {
     if (!ctx->gw.ensure(sizeof(double) * nn) || !ctx->gx.ensure(sizeof(double) * nn) ||

@@ -135,12 +135,29 @@ __global__ void k_rebin_lists(int64_t n, const int32_t *gnew, const uint32_t *fl
 }
 
 // each group's arrivals into ascending position: up to 8 in registers
-// (Batcher's odd-even merge network, 19 compare-exchanges), longer lists by
-// insertion sort in place (the lists of a push are short)
+// (Batcher's odd-even merge network, 19 compare-exchanges), up to 32 by a
+// bitonic network in registers, longer lists by insertion sort in place
 __device__ __forceinline__ void cx(int32_t &a, int32_t &b) {
   const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
   a = lo;
   b = hi;
+}
+template <int N>
+__device__ __forceinline__ void bitonic(int32_t (&v)[N]) {
+#pragma unroll
+  for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = i ^ j;
+        if (l > i) {
+          if ((i & k) == 0)
+            cx(v[i], v[l]);
+          else
+            cx(v[l], v[i]);
+        }
+      }
 }
 __global__ void k_rebin_sort(int64_t m, const int64_t *aoff, int32_t *alist) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
@@ -163,6 +180,16 @@ __global__ void k_rebin_sort(int64_t m, const int64_t *aoff, int32_t *alist) {
         if (i < k) a[i] = v[i];
       continue;
     }
+    if (k <= 32) {
+      int32_t v[32];
+#pragma unroll
+      for (int i = 0; i < 32; ++i) v[i] = i < k ? a[i] : INT32_MAX;
+      bitonic<32>(v);
+#pragma unroll
+      for (int i = 0; i < 32; ++i)
+        if (i < k) a[i] = v[i];
+      continue;
+    }
     for (int64_t i = 1; i < k; ++i) {
       const int32_t x = a[i];
       int64_t j = i - 1;
@@ -175,25 +202,49 @@ __global__ void k_rebin_sort(int64_t m, const int64_t *aoff, int32_t *alist) {
   }
 }
 
-__global__ void k_rebin_place(int64_t n, const int64_t *off, const int32_t *gold,
-                              const int32_t *gnew, const uint32_t *flag, const int64_t *mpre,
-                              const int64_t *aoff, const int32_t *alist, const uint32_t *leave,
-                              const int64_t *off_new, int32_t *perm, int32_t *err) {
+// Per group, once the scans are done, everything a particle of it needs:
+//   sbase  new position of a stayer at p is sbase + p - mpre[p] + (arrivals
+//          below p): off_new - off + (movers before the old segment)
+//   nbase  new offset; o0 old segment start; stay its stayers (for arrivals)
+//   a0, k  the group's sorted arrival list
+struct GroupRec {
+  int64_t sbase, nbase, o0, a0;
+  int32_t stay, k, ok, pad;
+};
+static_assert(sizeof(GroupRec) == 48, "the API allocates 48 bytes per group");
+__global__ void k_rebin_groups(int64_t m, int64_t n, const int64_t *off, const int64_t *mpre,
+                               const int64_t *aoff, const uint32_t *leave,
+                               const int64_t *off_new, GroupRec *rec) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o0 = off[g], o1 = off[g + 1];
+    GroupRec r;
+    r.ok = (o0 >= 0 && o1 >= o0 && o1 <= n) ? 1 : 0;  // inconsistent offsets (reported)
+    const int64_t c0 = r.ok ? o0 : 0;
+    r.sbase = off_new[g] - c0 + mpre[c0];
+    r.nbase = off_new[g];
+    r.o0 = c0;
+    r.stay = r.ok ? (int32_t)((o1 - o0) - (int64_t)leave[g]) : 0;
+    r.a0 = aoff[g];
+    r.k = (int32_t)(aoff[g + 1] - aoff[g]);
+    r.pad = 0;
+    rec[g] = r;
+  }
+}
+
+__global__ void k_rebin_place(int64_t n, const int32_t *gold, const int32_t *gnew,
+                              const int64_t *mpre, const GroupRec *rec, const int32_t *alist,
+                              int32_t *perm, int32_t *err) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
        p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t g = flag[p] ? gnew[p] : gold[p];
-    const int64_t o0 = off[g], o1 = off[g + 1];
-    if (o0 < 0 || o1 < o0 || o1 > n) continue;  // inconsistent offsets (reported)
-    const int32_t *a = alist + aoff[g];
-    const int64_t k = aoff[g + 1] - aoff[g];
-    int64_t pos;
-    if (!flag[p]) {
-      // stayers of g before p, then the arrivals into g before p
-      pos = off_new[g] + (p - o0) - (mpre[p] - mpre[o0]) + count_below(a, k, (int32_t)p);
-    } else {
-      const int64_t stay = (o1 - o0) - (int64_t)leave[g];
-      pos = off_new[g] + (p < o0 ? 0 : stay) + count_below(a, k, (int32_t)p);
-    }
+    const int32_t go = gold[p], gn = gnew[p];
+    const bool stayer = go == gn;
+    const int64_t mp = stayer ? mpre[p] : 0;
+    const GroupRec r = rec[gn];
+    if (!r.ok) continue;
+    const int64_t below = r.k ? count_below(alist + r.a0, r.k, (int32_t)p) : 0;
+    const int64_t pos = stayer ? r.sbase + p - mp + below
+                               : r.nbase + (p < r.o0 ? 0 : (int64_t)r.stay) + below;
     if (pos < 0 || pos >= n) {
       atomicCAS(err, 0, 1);
       continue;
@@ -214,12 +265,13 @@ hipError_t launch_scan(const uint32_t *counts, int64_t m, int64_t *tiles, int64_
                        hipStream_t s);
 
 // scratch: gold, gnew, alist int32[n]; flag uint32[n]; mpre int64[n + 1];
-// leave, arrive, acur, cnt uint32[m]; aoff int64[m + 1]; tiles of the scans
+// leave, arrive, acur, cnt uint32[m]; aoff int64[m + 1]; rec GroupRec[m];
+// tiles of the scans
 hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
                         const int32_t *cells_new, int64_t *off_new, int32_t *perm,
                         int32_t *gold, int32_t *gnew, int32_t *alist, uint32_t *flag,
                         int64_t *mpre, uint32_t *leave, uint32_t *arrive, uint32_t *acur,
-                        uint32_t *cnt, int64_t *aoff, int64_t *tiles, int32_t *err,
+                        uint32_t *cnt, int64_t *aoff, void *rec, int64_t *tiles, int32_t *err,
                         hipStream_t s) {
   hipError_t e;
   for (uint32_t *b : {leave, arrive, acur})
@@ -240,8 +292,10 @@ hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const 
     hipLaunchKernelGGL(k_rebin_lists, dim3(grid_of(n)), dim3(256), 0, s, n, gnew, flag, aoff,
                        acur, alist);
     hipLaunchKernelGGL(k_rebin_sort, dim3(grid_of(m)), dim3(256), 0, s, m, aoff, alist);
-    hipLaunchKernelGGL(k_rebin_place, dim3(grid_of(n)), dim3(256), 0, s, n, off, gold, gnew,
-                       flag, mpre, aoff, alist, leave, off_new, perm, err);
+    hipLaunchKernelGGL(k_rebin_groups, dim3(grid_of(m)), dim3(256), 0, s, m, n, off, mpre, aoff,
+                       leave, off_new, reinterpret_cast<GroupRec *>(rec));
+    hipLaunchKernelGGL(k_rebin_place, dim3(grid_of(n)), dim3(256), 0, s, n, gold, gnew, mpre,
+                       reinterpret_cast<const GroupRec *>(rec), alist, perm, err);
   }
   return hipGetLastError();
 }
