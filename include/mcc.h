@@ -56,8 +56,8 @@ typedef enum { MCC_TA77 = 0, MCC_N97 = 1 } mcc_method;
 typedef enum { MCC_FP64 = 0, MCC_FP32_KINEMATICS = 1 } mcc_precision;
 typedef enum { MCC_FAIL_RESET = 0, MCC_FAIL_KEEP = 1 } mcc_fail_policy;
 /* Binary pairing of the scatter.  ORDER_N: the TA77 random pairs of Fig. 1
- * (Sec. 3.2), s of Eq. (sab_TA77) with w_max N_min / dV.  NXN: every pair of
- * the collision once (Sec. 3.1), s of Eq. (sab_weighted) with w_max / dV and
+ * (Sec. 3.2), s of Eq. (12) with w_max N_min / dV.  NXN: every pair of
+ * the collision once (Sec. 3.1), s of Eq. (10) with w_max / dV and
  * the same w_min/w_max acceptance; the pairs run in rounds of disjoint pairs
  * over the shuffled lists (intra-species: the circle schedule on N rounded
  * up to even, N - 1 or N rounds; inter-species: round r pairs list-a entry i

@@ -35,7 +35,7 @@
  *     counter = {index, cell, step_lo, step_hi16<<16 | collision<<8 | purpose}.
  *   - Random pairs: each species list is ordered by (Philox word, local index).
  *   - N x N pairing (Sec. 3.1, optional): every pair of the collision once,
- *     s of Eq. (sab_weighted) with w_max / dV.  The pairs are taken over the
+ *     s of Eq. (10) with w_max / dV.  The pairs are taken over the
  *     shuffled lists in rounds: intra-species, the circle schedule on N
  *     rounded up to even (round r: (r, pad) and ((r+m) mod R, (r-m) mod R),
  *     R = rounds), pairs with the pad skipped; inter-species, round r pairs

@@ -983,7 +983,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       const double nmin_dv = nmin / dV, nmin_dv_b = (double)(nb - 1) / dV;
       const bool odd = intra && (na & 1);
       if constexpr (NXN) {
-        // N x N (Sec. 3.1): every pair once with s of Eq. (sab_weighted)
+        // N x N (Sec. 3.1): every pair once with s of Eq. (10)
         // (w_max / dV), in rounds of disjoint pairs, one barrier per round.
         //  intra: the circle schedule on np = N rounded up to even; round r
         //         pairs (r, np-1) and ((r+m) mod R, (r-m) mod R), 0 < m <

@@ -1,7 +1,7 @@
 """N x N pairing (Sec. 3.1) on the GPU against the oracle's N x N step.
 
 Every pair of a collision is scattered once, in the oracle's order (rounds of
-disjoint pairs over the shuffled lists), with s of Eq. (sab_weighted) and the
+disjoint pairs over the shuffled lists), with s of Eq. (10) and the
 same correction as the order-N step.  Covered: every size bucket and layout
 (compact LDS up to 4096 particles, global scratch above), ragged and
 one-particle species, empty species, the weight classes, TA77, the

@@ -1,7 +1,7 @@
 """The oracle's duplicity pairing (the variant of Higginson et al. that the
 paper describes after Sec. 3.2) pinned to what the paper fixes.
 
-The pairs are the order-N pairs; an inter-species pair's s is Eq. (sab_TA77)
+The pairs are the order-N pairs; an inter-species pair's s is Eq. (12)
 with N_max / D in place of N_min, D the number of pairs its fewer-population
 particle takes in the step.
 
@@ -10,12 +10,11 @@ particle takes in the step.
 - Otherwise D depends on the shuffle.  For a 3 + 2 cell the second particle
   of the shorter list takes one pair (D = 1) and the first takes two
   (D = 2).  Grouping replica cells by their shuffled lists, the mean velocity
-  change of every particle in every group is the drag sum of Eq. (LDF_drag)
+  change of every particle in every group is the drag sum of Eq. (8)
   over that group's pairs with the duplicity s; the order-N s (N_min), the
   N_max s without the division by D, and the N x N s (1) each fit far worse.
 """
 import math
-from itertools import permutations
 
 import numpy as np
 import pytest

@@ -1,12 +1,12 @@
 """The oracle's N x N pairing (Sec. 3.1) pinned to what the paper fixes.
 
 - With two particles (one pair) the N x N and the order-N steps are the same
-  computation: N_min = 1 in Eq. (sab_TA77) makes it Eq. (sab_weighted).
+  computation: N_min = 1 in Eq. (12) makes it Eq. (10).
 - The number of pairs is the number of unordered pairs, n (n - 1) / 2 per
   intra-species collision and N_a N_b per inter-species one.
 - The expected velocity change of every particle over one step is the drag
-  sum of Eq. (LDF_drag) over all its partners j, -(mu / m_i) P_i (1 - e^-s)
-  u_ij with s of Eq. (sab_weighted) and P_i = 1 for the lighter-weight
+  sum of Eq. (8) over all its partners j, -(mu / m_i) P_i (1 - e^-s)
+  u_ij with s of Eq. (10) and P_i = 1 for the lighter-weight
   particle of the pair, w_min / w_max for the heavier (the rejection that
   gives the heavier one s_ji on average).  N97's mean deflection is
   <cos chi> = e^-s; the sum is taken at the initial velocities (first order
