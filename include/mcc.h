@@ -143,7 +143,8 @@ void mcc_destroy(mcc_ctx *ctx);
  * error code latched since the last call (0 if none), then clear it.
  * Codes: 1 offsets not monotone or out of [0, n]; 2 cell larger than
  * MCC_MAX_CELL; 3 cell or species id out of range (unsorted entry,
- * re-binning). */
+ * re-binning); 4 a weight not positive and finite (the sorted entries check
+ * every call, a plan once when it is created). */
 mcc_status mcc_device_error(mcc_ctx *ctx, int32_t *code);
 
 /*

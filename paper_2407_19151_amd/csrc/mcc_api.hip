@@ -33,6 +33,7 @@ const void *const *mcc_kernel_table_rel_dup();
 namespace mcc {
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_zero_stats(mcc_stats *st, hipStream_t s);
+hipError_t launch_check_weights(int64_t n, const double *w, int32_t *err, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
 hipError_t launch_inc_u64(uint64_t *p, hipStream_t s);
 hipError_t launch_bucket_cells(const int64_t *offsets, int32_t n_cells, int32_t S, int64_t n,
@@ -513,6 +514,7 @@ mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t 
   HIP_TRY(launch_fill_u32(ctx->counts.as<uint32_t>(), 0u, NBUCKET, s));
   if (stats) HIP_TRY(launch_zero_stats(stats, s));
   if (n_cells == 0) return finish(ctx);
+  HIP_TRY(launch_check_weights(n, weights, ctx->err, s));
   HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, ctx->lists.as<int32_t>(),
                               ctx->counts.as<uint32_t>(), cell_corr_pairs, ctx->err, s));
   st = launch_buckets(ctx, A, mode_of(p, A), n_cells, ctx->lists.as<int32_t>(),
@@ -553,6 +555,7 @@ mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells, int3
   A.dlnl = coulomb_log_tangent != 0.0 ? coulomb_log_tangent / coulomb_log : 0.0;
   A.write_primal = update_primal ? 1 : 0;
   hipStream_t s = ctx->stream;
+  HIP_TRY(launch_check_weights(n, weights, ctx->err, s));
   HIP_TRY(launch_fill_u32(ctx->counts.as<uint32_t>(), 0u, NBUCKET, s));
   if (stats) HIP_TRY(launch_zero_stats(stats, s));
   if (n_cells == 0) return finish(ctx);
@@ -812,6 +815,13 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
       mcc_plan_destroy(pl);
       return MCC_ERR_OOM;
     }
+  // the weights are bound to the plan: checked once here (positive and
+  // finite; a violation is latched as data error 4) and never again per step
+  e = launch_check_weights(n, weights, ctx->err, s);
+  if (e != hipSuccess) {
+    mcc_plan_destroy(pl);
+    return from_hip(e);
+  }
   // the weights are bound to the plan: their per-(cell, species) sums, range
   // and class, and the descending-weight order, are computed once here (with
   // the chosen variants, so the sums round as in a step) and read by every

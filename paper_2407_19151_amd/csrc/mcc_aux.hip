@@ -17,6 +17,18 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t v, int64_t n) {
     p[i] = v;
 }
 
+// weights must be positive and finite (a species' density is sum w / dV)
+__global__ void k_check_weights(int64_t n, const double *w, int32_t *err) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = w[i];
+    if (!(x > 0.0) || x == __builtin_inf()) {
+      atomicCAS(err, 0, 4);
+      return;
+    }
+  }
+}
+
 __global__ void k_zero_stats(mcc_stats *s) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     s->pairs = s->corr_pairs = s->failed = s->collisions = 0ull;
@@ -323,6 +335,12 @@ static inline int grid_for(int64_t n, int tpb) {
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n, 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_weights(int64_t n, const double *w, int32_t *err, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_weights, dim3(grid_for(n, 256)), dim3(256), 0, s, n, w, err);
   return hipGetLastError();
 }
 

@@ -94,6 +94,60 @@ def test_parity_large_global_scratch_cells(ctx):
     _parity(ctx, wl, 2)
 
 
+def test_degenerate_steps_leave_the_state_unchanged(ctx):
+    """dt = 0 and lnL = 0 make every s zero; a cold cell (all velocities
+    equal) has no relative velocity: the step must return the input bit for
+    bit, with no correction pairs and no failures.  A cell where a pair has
+    identical velocities is otherwise stepped like any other (against the
+    oracle)."""
+    from paper_2407_19151_amd import native, runner
+    wl = custom_workload([(20, 10), (5, 5), (300, 200)], seed=49)
+    for over in (dict(dt=0.0), dict(coulomb_log=0.0)):
+        w2 = wl.copy()
+        for k, v in over.items():
+            setattr(w2, k, v)
+        dw = runner.DeviceWorkload(w2)
+        runner.collide_sorted(ctx, dw, 0)
+        assert ctx.device_error() == 0
+        assert np.array_equal(dw.velocities(), w2.velocities()), over
+        st = native.read_stats(dw.stats)
+        assert st["corr_pairs"] == 0 and st["failed"] == 0
+    cold = wl.copy()
+    cold.vx = np.full(cold.n, 0.3)
+    cold.vy = np.full(cold.n, -0.1)
+    cold.vz = np.full(cold.n, 0.2)
+    dw = runner.DeviceWorkload(cold)
+    runner.collide_sorted(ctx, dw, 0)
+    assert np.array_equal(dw.velocities(), cold.velocities())
+    twin = wl.copy()
+    twin.vx = twin.vx.copy()
+    twin.vy = twin.vy.copy()
+    twin.vz = twin.vz.copy()
+    for a in (twin.vx, twin.vy, twin.vz):
+        a[1] = a[0]   # two particles of cell 0, species 0, at one velocity
+    _parity(ctx, twin, 3)
+
+
+@pytest.mark.parametrize("bad", [0.0, -1.0, float("nan"), float("inf")])
+def test_weight_not_positive_and_finite_is_reported(ctx, bad):
+    """Weights are densities (sum w / dV): a zero, negative, NaN or infinite
+    weight is a data error (code 4), reported by the plain call and once by a
+    plan's creation; the oracle rejects the same input."""
+    import oracle as orc
+    from paper_2407_19151_amd import runner
+    wl = custom_workload([(20, 10), (5, 5)], seed=50)
+    wl.w = wl.w.copy()
+    wl.w[7] = bad
+    dw = runner.DeviceWorkload(wl)
+    runner.collide_sorted(ctx, dw, 0)
+    assert ctx.device_error() == 4
+    plan = runner.make_plan(ctx, runner.DeviceWorkload(wl), autotune=False)
+    plan.close()
+    assert ctx.device_error() == 4
+    with pytest.raises(orc.OracleError):
+        oracle_step(wl.copy(), 0)
+
+
 def test_parity_at_the_maximum_cell_and_one_past_it(ctx):
     """A cell of exactly MCC_MAX_CELL particles is stepped like any other; a
     cell one particle larger is skipped (left unchanged) and reported as code
