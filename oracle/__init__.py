@@ -24,6 +24,7 @@ N97 = 1
 ORDER_N = 0
 NXN = 1
 DUPLICITY = 2
+HARD_SPHERE = 2   # method: isotropic collisions with probability 1 - exp(-s)
 
 _lib = None
 
@@ -73,11 +74,11 @@ def lib():
         L.oracle_scatter_pair.restype = None
         L.oracle_collide_sorted.argtypes = (
             [i64, i32, i32, P, P, P, i32, P, P, P, P, P, P, P, f64, f64, f64, u64, u64,
-             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, i32, P, P, P])
+             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, i32, P, P, P, P])
         L.oracle_collide_sorted.restype = C.c_int
         L.oracle_collide.argtypes = (
             [i64, P, P, i32, i32, P, P, i32, P, P, P, P, P, P, P, f64, f64, f64, u64, u64,
-             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, P, P])
+             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, P, P, P])
         L.oracle_collide.restype = C.c_int
         L.oracle_collide_sorted_traced.argtypes = (
             [i64, i32, i32, P, P, P, i32, P, P, P, P, P, P, f64, f64, f64, u64, u64,
@@ -172,16 +173,26 @@ def _coll_arrays(collisions):
     return ca, cb
 
 
+def _sigma(cross_section, n_coll):
+    if cross_section is None:
+        return None
+    sg = _f64(np.broadcast_to(np.asarray(cross_section, dtype=np.float64), (n_coll,)))
+    return sg.copy()
+
+
 def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
                    coulomb_log, seed, step, method=N97, relativistic=False,
                    correction=True, sort_by_weight=True, max_passes=1,
                    keep_on_fail=False, f_E=0.05, eps0=1.0, c=math.inf,
                    cell_volume=1.0, cells: Optional[Sequence[int]] = None,
-                   n_cells: Optional[int] = None, pairing: int = ORDER_N) -> dict:
+                   n_cells: Optional[int] = None, pairing: int = ORDER_N,
+                   cross_section=None) -> dict:
     """One step on (cell, species)-grouped arrays; vx, vy, vz updated in place.
     pairing: ORDER_N (Sec. 3.2), NXN (every pair once, Sec. 3.1) or
     DUPLICITY (order-N pairs, inter-species s with N_max / D, the variant the
-    paper attributes to Higginson et al.)."""
+    paper attributes to Higginson et al.).
+    method HARD_SPHERE needs cross_section (one per collision, or a scalar):
+    charges, coulomb_log and eps0 are then unused."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     mass = _f64(mass)
     charge = _f64(charge)
@@ -196,6 +207,7 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
     if not np.isscalar(cell_volume):
         cv = _f64(cell_volume)
     cl = None if cells is None else np.ascontiguousarray(cells, dtype=np.int32)
+    sg = _sigma(cross_section, len(collisions))
     counters = np.zeros(4, dtype=np.int64)
     diag = np.zeros(2)
     ccp = np.zeros(max(n_cells, 1), dtype=np.int32)
@@ -206,7 +218,7 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
         _p(ca), _p(cb), _p(w), _p(vx), _p(vy), _p(vz), _p(cv), cvs, dt, coulomb_log,
         seed, step, method, int(pairing), int(relativistic), int(correction),
         int(sort_by_weight), max_passes, int(keep_on_fail), f_E, eps0, c, _p(cl),
-        0 if cl is None else cl.shape[0], _p(counters), _p(diag), _p(ccp))
+        0 if cl is None else cl.shape[0], _p(counters), _p(diag), _p(ccp), _p(sg))
     if rc != 0:
         raise OracleError("oracle_collide_sorted returned %d" % rc)
     return dict(pairs=int(counters[0]), corr_pairs=int(counters[1]),
@@ -218,7 +230,7 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
 def collide(cells, species, n_cells, mass, charge, collisions, w, vx, vy, vz, *, dt,
             coulomb_log, seed, step, method=N97, relativistic=False, correction=True,
             sort_by_weight=True, max_passes=1, keep_on_fail=False, f_E=0.05, eps0=1.0,
-            c=math.inf, cell_volume=1.0, pairing: int = ORDER_N) -> dict:
+            c=math.inf, cell_volume=1.0, pairing: int = ORDER_N, cross_section=None) -> dict:
     """One step on particles in any order; vx, vy, vz updated in place."""
     cells = np.ascontiguousarray(cells, dtype=np.int32)
     species = np.ascontiguousarray(species, dtype=np.int32)
@@ -226,6 +238,7 @@ def collide(cells, species, n_cells, mass, charge, collisions, w, vx, vy, vz, *,
     charge = _f64(charge)
     S = mass.shape[0]
     ca, cb = _coll_arrays(collisions)
+    sg = _sigma(cross_section, len(collisions))
     cv = None
     cvs = float(cell_volume) if np.isscalar(cell_volume) else 0.0
     if not np.isscalar(cell_volume):
@@ -240,7 +253,7 @@ def collide(cells, species, n_cells, mass, charge, collisions, w, vx, vy, vz, *,
         len(collisions), _p(ca), _p(cb), _p(w), _p(vx), _p(vy), _p(vz), _p(cv), cvs,
         dt, coulomb_log, seed, step, method, int(pairing), int(relativistic),
         int(correction), int(sort_by_weight), max_passes, int(keep_on_fail), f_E, eps0, c,
-        _p(counters), _p(diag), _p(ccp))
+        _p(counters), _p(diag), _p(ccp), _p(sg))
     if rc != 0:
         raise OracleError("oracle_collide returned %d" % rc)
     return dict(pairs=int(counters[0]), corr_pairs=int(counters[1]),

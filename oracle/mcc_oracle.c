@@ -57,6 +57,15 @@
  *   - Relativistic scatter (paper silent): rotation of the centre-of-momentum
  *     momentum of the pair by the sampled angles, with s from the invariant
  *     collision rate (reduces to Eq. (12) as c -> infinity).
+ *   - Hard-sphere process (optional; the non-Coulomb use of the same
+ *     weighting and correction that the paper's summary names, with the
+ *     collision integral of Sec. 2 for a total cross-section sigma and an
+ *     isotropic differential one, I = sigma / 4 pi): the normalized path
+ *     length is s = f sigma n_eff |u| dt, n_eff the density factor the
+ *     pairing gives Eq. (12) or (10) (w_max N_min / dV, w_max / dV, or
+ *     w_max (N_max / D) / dV).  The pair collides with probability
+ *     1 - exp(-s) (u0 < 1 - exp(-s)), then 1 - cos chi = 2 u1 (isotropic),
+ *     azimuth and acceptance as for the Coulomb methods.  Non-relativistic.
  */
 #include <math.h>
 #include <stdint.h>
@@ -69,6 +78,7 @@
 
 #define ORC_TA77 0
 #define ORC_N97 1
+#define ORC_HARD_SPHERE 2
 #define ORC_ORDER_N 0
 #define ORC_NXN 1
 #define ORC_DUPLICITY 2
@@ -315,6 +325,7 @@ typedef struct {
   int32_t method, rel, corr, sortw, max_passes, keep_on_fail;
   double fE;
   int32_t pairing; /* ORC_ORDER_N, ORC_NXN or ORC_DUPLICITY */
+  const double *sigma; /* [n_coll] cross-sections (ORC_HARD_SPHERE only) */
 } cfg_t;
 
 typedef struct {
@@ -362,15 +373,26 @@ static void scatter_pair_nr(const cfg_t *g, uint32_t cell, int coll,
   double u[3] = {vi[0] - vj[0], vi[1] - vj[1], vi[2] - vj[2]};
   double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   if (um == 0.0) return;
-  double mu = mi * mj / (mi + mj);
   double wmax = wi > wj ? wi : wj;
-  double s = f * (qi * qi * qj * qj * g->lnL) * (wmax * nmin / dV) * g->dt /
-             (4.0 * PI * g->eps0 * g->eps0 * mu * mu * um * um * um);
-  if (!(s > 0.0)) return;
   uint32_t r[4];
-  draw4(g->seed, pair_k, cell, g->step, coll, PURPOSE_PAIR, r);
-  double st;
-  double oc = oracle_sample_angle(g->method, s, unif(r[0]), unif(r[1]), &st);
+  double st, oc;
+  if (g->method == ORC_HARD_SPHERE) {
+    /* s = f sigma n_eff |u| dt: the expected number of collisions of the
+     * pair in the step; at least one happens with probability 1 - e^-s */
+    double s = f * g->sigma[coll] * (wmax * nmin / dV) * um * g->dt;
+    if (!(s > 0.0)) return;
+    draw4(g->seed, pair_k, cell, g->step, coll, PURPOSE_PAIR, r);
+    if (!(unif(r[0]) < -expm1(-s))) return;
+    oc = 2.0 * unif(r[1]); /* cos chi uniform on (-1, 1) */
+    st = sqrt(oc * (2.0 - oc));
+  } else {
+    double mu = mi * mj / (mi + mj);
+    double s = f * (qi * qi * qj * qj * g->lnL) * (wmax * nmin / dV) * g->dt /
+               (4.0 * PI * g->eps0 * g->eps0 * mu * mu * um * um * um);
+    if (!(s > 0.0)) return;
+    draw4(g->seed, pair_k, cell, g->step, coll, PURPOSE_PAIR, r);
+    oc = oracle_sample_angle(g->method, s, unif(r[0]), unif(r[1]), &st);
+  }
   double phi = 2.0 * PI * unif(r[2]);
   double du[3];
   oracle_rotate(u, st, oc, phi, du);
@@ -941,7 +963,9 @@ static int check_common(int64_t n, int32_t n_cells, int32_t n_species,
   for (int64_t i = 0; i < n; ++i)
     if (!(w[i] > 0.0) || !isfinite(w[i])) return ORC_ERR_INVALID;
   if (!isfinite(dt) || dt < 0.0 || !isfinite(lnL) || lnL < 0.0) return ORC_ERR_INVALID;
-  if (method != ORC_TA77 && method != ORC_N97) return ORC_ERR_INVALID;
+  if (method != ORC_TA77 && method != ORC_N97 && method != ORC_HARD_SPHERE)
+    return ORC_ERR_INVALID;
+  if (method == ORC_HARD_SPHERE && rel) return ORC_ERR_INVALID;
   if (max_passes < 1) return ORC_ERR_INVALID;
   if (!(fE > 0.0) || !(fE < 1.0)) return ORC_ERR_INVALID;
   if (!(eps0 > 0.0)) return ORC_ERR_INVALID;
@@ -969,20 +993,27 @@ int oracle_collide_sorted(
     int32_t pairing, int32_t relativistic, int32_t moment_correction,
     int32_t sort_by_weight, int32_t max_passes, int32_t keep_on_fail, double f_E,
     double eps0, double c, const int32_t *cell_list, int32_t n_list,
-    int64_t *counters, double *diag, int32_t *cell_corr_pairs) {
+    int64_t *counters, double *diag, int32_t *cell_corr_pairs,
+    const double *cross_section) {
   int rc = check_common(n, n_cells, n_species, mass, charge, n_coll, coll_a,
                         coll_b, w, dt, coulomb_log, method, relativistic,
                         max_passes, f_E, eps0, c, cell_volume, cell_volume_scalar);
   if (rc) return rc;
   if (pairing != ORC_ORDER_N && pairing != ORC_NXN && pairing != ORC_DUPLICITY)
     return ORC_ERR_INVALID;
+  if (method == ORC_HARD_SPHERE) {
+    if (n_coll > 0 && !cross_section) return ORC_ERR_INVALID;
+    for (int k = 0; k < n_coll; ++k)
+      if (!(cross_section[k] >= 0.0) || !isfinite(cross_section[k])) return ORC_ERR_INVALID;
+  }
   const int64_t S = n_species;
   if (offsets[0] != 0 || offsets[(int64_t)n_cells * S] != n) return ORC_ERR_INVALID;
   for (int64_t i = 0; i < (int64_t)n_cells * S; ++i)
     if (offsets[i + 1] < offsets[i]) return ORC_ERR_INVALID;
   cfg_t g = {n_species, mass, charge, n_coll, coll_a, coll_b, dt, coulomb_log,
              eps0, c, seed, step, method, relativistic, moment_correction,
-             sort_by_weight, max_passes, keep_on_fail, f_E, pairing};
+             sort_by_weight, max_passes, keep_on_fail, f_E, pairing,
+             cross_section};
   stats_t st;
   memset(&st, 0, sizeof(st));
   int32_t nl = cell_list ? n_list : n_cells;
@@ -1031,7 +1062,8 @@ int oracle_collide(int64_t n, const int32_t *cells, const int32_t *species,
                    int32_t pairing, int32_t relativistic, int32_t moment_correction,
                    int32_t sort_by_weight, int32_t max_passes,
                    int32_t keep_on_fail, double f_E, double eps0, double c,
-                   int64_t *counters, double *diag, int32_t *cell_corr_pairs) {
+                   int64_t *counters, double *diag, int32_t *cell_corr_pairs,
+                   const double *cross_section) {
   if (n < 0 || n_cells < 0 || n_species < 1) return ORC_ERR_INVALID;
   const int64_t S = n_species, nk = (int64_t)n_cells * S;
   for (int64_t i = 0; i < n; ++i)
@@ -1061,7 +1093,7 @@ int oracle_collide(int64_t n, const int32_t *cells, const int32_t *species,
       gy, gz, cell_volume, cell_volume_scalar, dt, coulomb_log, seed, step,
       method, pairing, relativistic, moment_correction, sort_by_weight,
       max_passes, keep_on_fail, f_E, eps0, c, NULL, 0, counters, diag,
-      cell_corr_pairs);
+      cell_corr_pairs, cross_section);
   if (rc == ORC_OK) {
     for (int64_t j = 0; j < n; ++j) {
       vx[perm[j]] = gx[j];
@@ -1113,6 +1145,7 @@ void oracle_scatter_pair(int32_t method, int32_t relativistic, double s_factor,
   g.step = step;
   g.method = method;
   g.rel = relativistic;
+  if (method != ORC_TA77 && method != ORC_N97) return; /* Coulomb methods only */
   if (relativistic)
     scatter_pair_rel(&g, cell, coll, pair_k, s_factor, nmin, dV, mi, qi, mj, qj,
                      wi, wj, vi, vj);
@@ -1141,7 +1174,7 @@ int oracle_collide_sorted_traced(
       n, n_cells, n_species, offsets, mass, charge, n_coll, coll_a, coll_b, w,
       vx, vy, vz, NULL, cell_volume_scalar, dt, coulomb_log, seed, step, method,
       ORC_ORDER_N, relativistic, 1, sort_by_weight, 1, 0, f_E, 1.0, c, NULL, 0,
-      NULL, NULL, NULL);
+      NULL, NULL, NULL, NULL);
   g_trace = NULL;
   return rc;
 }
