@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--nxn", action="store_true",
                     help="only time the N x N pairing (Sec. 3.1) against order-N on 1024 cells "
                          "of 256 electrons + 256 ions, and exit")
+    ap.add_argument("--hard-sphere", action="store_true",
+                    help="only time the hard-sphere process against N97 (both FP64) on the "
+                         "65,536-cell population, and exit")
     ap.add_argument("--paper-test3-curve", action="store_true",
                     help="relax the paper's T3b and T3c to equilibrium (1.1e6 steps each), "
                          "sampling T_e and T_i, and exit")
@@ -242,6 +245,39 @@ def nxn_bench(steps, warmup):
         torch.cuda.empty_cache()
 
 
+def hard_sphere_bench(steps, warmup):
+    """The hard-sphere process (about 5 % collision probability per particle
+    and collision) against N97 Coulomb scattering, both FP64, on the
+    65,536-cell population: step time, particle-collisions per second, and
+    the duration of each size bucket's kernel with its algorithmic HBM rate
+    (64 B per particle)."""
+    import torch
+    from paper_2407_19151_amd import native, runner
+    from paper_2407_19151_amd import workloads as W
+    ctx = native.Context(0)
+    base = W.config3()
+    per_bucket_n = bucket_particles(base)
+    for wl in (W.hard_sphere(base), base):
+        dw = runner.DeviceWorkload(wl)
+        plan = runner.make_plan(ctx, dw, params=runner.params_for(wl), autotune=False)
+        ms, _ = time_plan(plan, steps, warmup)
+        bms = time_buckets(plan, sorted(per_bucket_n), steps)
+        plan.close()
+        assert ctx.device_error() == 0
+        dom = max(bms, key=lambda b: bms[b])
+        print(json.dumps({
+            "workload": wl.name, "method": "hard_sphere" if wl.method == W.HARD_SPHERE else "n97",
+            "dtype": "f64", "ms_per_step": ms,
+            "particle_collisions_per_s": wl.particle_collisions_per_step() / (ms * 1e-3),
+            "bucket_ms": {str(b): round(v, 4) for b, v in bms.items()},
+            "dominant_bucket": dom, "dominant_ms": bms[dom],
+            "dominant_frac_of_8TBs": BYTES_PER_PARTICLE_STEP * per_bucket_n[dom]
+            / (bms[dom] * 1e-3) / 8e12,
+            "steps": steps}), flush=True)
+        del dw
+        torch.cuda.empty_cache()
+
+
 def rebin_bench(steps, warmup):
     """mcc_rebin on the 65,536-cell population after a push that moves a
     fraction of the particles to a neighbouring cell (10 % of those jump
@@ -352,6 +388,9 @@ def main():
         return
     if args.rebin:
         rebin_bench(args.steps, args.warmup)
+        return
+    if args.hard_sphere:
+        hard_sphere_bench(args.steps, args.warmup)
         return
     if args.paper_test1 or args.paper_test2 or args.paper_test3:
         paper_tests(1 if args.paper_test1 else 2 if args.paper_test2 else 3, args.steps, args.warmup)

@@ -52,7 +52,20 @@ typedef enum {
   MCC_ERR_DATA = -5         /* device-side data check failed (see mcc_device_error) */
 } mcc_status;
 
-typedef enum { MCC_TA77 = 0, MCC_N97 = 1 } mcc_method;
+/* Scattering process of a pair, given its normalized path length s.
+ * TA77, N97: small-angle Coulomb scattering; s of Eq. (12) (Eq. (10) for
+ * N x N pairing) sets the spread of the centre-of-mass angle (Sec. 3.2).
+ * HARD_SPHERE: a non-Coulomb process of the collision integral of Sec. 2,
+ * the extension the paper's summary names: elastic scattering with the
+ * collision's constant total cross-section and isotropic angles.
+ * s = sigma n_eff |u| dt, n_eff the density factor the pairing gives the
+ * Coulomb s (w_max N_min / dV, w_max / dV, or w_max (N_max / D) / dV), is
+ * read as the expected number of collisions: the pair collides with
+ * probability 1 - exp(-s).  Weighting, acceptance and moment correction are
+ * the Coulomb ones.  Charges, the Coulomb logarithm and eps0 are unused.
+ * FP64 precision and non-relativistic only (otherwise MCC_ERR_UNSUPPORTED);
+ * not available to mcc_collide_sorted_jvp. */
+typedef enum { MCC_TA77 = 0, MCC_N97 = 1, MCC_HARD_SPHERE = 2 } mcc_method;
 typedef enum { MCC_FP64 = 0, MCC_FP32_KINEMATICS = 1 } mcc_precision;
 typedef enum { MCC_FAIL_RESET = 0, MCC_FAIL_KEEP = 1 } mcc_fail_policy;
 /* Binary pairing of the scatter.  ORDER_N: the TA77 random pairs of Fig. 1
@@ -89,6 +102,8 @@ typedef struct {
 typedef struct {
   int32_t a;
   int32_t b;
+  double cross_section; /* MCC_HARD_SPHERE: total cross-section (area, caller's units),
+                           finite and >= 0; ignored by the Coulomb methods */
 } mcc_collision;
 
 typedef struct {

@@ -168,13 +168,18 @@ class OracleError(RuntimeError):
 
 
 def _coll_arrays(collisions):
-    ca = np.array([a for a, _ in collisions], dtype=np.int32)
-    cb = np.array([b for _, b in collisions], dtype=np.int32)
+    ca = np.array([c[0] for c in collisions], dtype=np.int32)
+    cb = np.array([c[1] for c in collisions], dtype=np.int32)
     return ca, cb
 
 
-def _sigma(cross_section, n_coll):
+def _sigma(cross_section, collisions):
+    """Per-collision cross-sections: the argument, else the third entry of
+    (a, b, sigma) collision tuples, else none."""
+    n_coll = len(collisions)
     if cross_section is None:
+        if n_coll and all(len(c) > 2 for c in collisions):
+            return _f64([c[2] for c in collisions]).copy()
         return None
     sg = _f64(np.broadcast_to(np.asarray(cross_section, dtype=np.float64), (n_coll,)))
     return sg.copy()
@@ -207,7 +212,7 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
     if not np.isscalar(cell_volume):
         cv = _f64(cell_volume)
     cl = None if cells is None else np.ascontiguousarray(cells, dtype=np.int32)
-    sg = _sigma(cross_section, len(collisions))
+    sg = _sigma(cross_section, collisions)
     counters = np.zeros(4, dtype=np.int64)
     diag = np.zeros(2)
     ccp = np.zeros(max(n_cells, 1), dtype=np.int32)
@@ -238,7 +243,7 @@ def collide(cells, species, n_cells, mass, charge, collisions, w, vx, vy, vz, *,
     charge = _f64(charge)
     S = mass.shape[0]
     ca, cb = _coll_arrays(collisions)
-    sg = _sigma(cross_section, len(collisions))
+    sg = _sigma(cross_section, collisions)
     cv = None
     cvs = float(cell_volume) if np.isscalar(cell_volume) else 0.0
     if not np.isscalar(cell_volume):

@@ -199,7 +199,12 @@ mcc_status check_step(int64_t n, int32_t n_cells, int32_t n_species, const doubl
     if (coll[k].a < 0 || coll[k].a >= n_species || coll[k].b < 0 || coll[k].b >= n_species)
       return MCC_ERR_INVALID;
   if (!std::isfinite(dt) || dt < 0.0 || !std::isfinite(lnL) || lnL < 0.0) return MCC_ERR_INVALID;
-  if (p->method != MCC_TA77 && p->method != MCC_N97) return MCC_ERR_INVALID;
+  if (p->method != MCC_TA77 && p->method != MCC_N97 && p->method != MCC_HARD_SPHERE)
+    return MCC_ERR_INVALID;
+  if (p->method == MCC_HARD_SPHERE)
+    for (int k = 0; k < n_coll; ++k)
+      if (!(coll[k].cross_section >= 0.0) || !std::isfinite(coll[k].cross_section))
+        return MCC_ERR_INVALID;
   if (p->precision != MCC_FP64 && p->precision != MCC_FP32_KINEMATICS) return MCC_ERR_INVALID;
   if (p->on_failure != MCC_FAIL_RESET && p->on_failure != MCC_FAIL_KEEP) return MCC_ERR_INVALID;
   if (p->max_passes < 1) return MCC_ERR_INVALID;
@@ -211,6 +216,8 @@ mcc_status check_step(int64_t n, int32_t n_cells, int32_t n_species, const doubl
   if (!(p->eps0 > 0.0) || !std::isfinite(p->eps0)) return MCC_ERR_INVALID;
   if (p->relativistic && !(p->c > 0.0 && std::isfinite(p->c))) return MCC_ERR_INVALID;
   if (p->relativistic && p->precision != MCC_FP64) return MCC_ERR_UNSUPPORTED;
+  if (p->method == MCC_HARD_SPHERE && (p->relativistic || p->precision != MCC_FP64))
+    return MCC_ERR_UNSUPPORTED;
   if (!cell_volume && !(dVs > 0.0 && std::isfinite(dVs))) return MCC_ERR_INVALID;
   return MCC_OK;
 }
@@ -252,9 +259,12 @@ void fill_args(CollideArgs &A, int64_t n, int32_t n_cells, int32_t S, const int6
     CollConst &C = A.coll[k];
     C.a = a;
     C.b = b;
-    // Eq. (12) without the per-pair factors f, w_max, N_min, dV and |u|^3
+    // Eq. (12) without the per-pair factors f, w_max, N_min, dV and |u|^3;
+    // for hard spheres s = sigma n_eff |u| dt without f, w_max, N_min, dV, |u|
     const double base = qa * qa * qb * qb * lnL * dt / (4.0 * pi * p->eps0 * p->eps0);
-    C.coef = p->relativistic ? base : base / (mu * mu);
+    C.coef = p->method == MCC_HARD_SPHERE ? coll[k].cross_section * dt
+             : p->relativistic            ? base
+                                          : base / (mu * mu);
     C.fa = mb / (ma + mb);
     C.fb = ma / (ma + mb);
   }
@@ -539,7 +549,8 @@ mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells, int3
   if (n > 0 && (!tx || !ty || !tz)) return MCC_ERR_INVALID;
   if (!std::isfinite(coulomb_log_tangent)) return MCC_ERR_INVALID;
   if (coulomb_log_tangent != 0.0 && !(coulomb_log > 0.0)) return MCC_ERR_INVALID;
-  if (p->relativistic || p->precision != MCC_FP64 || p->pairing != MCC_PAIRING_ORDER_N)
+  if (p->relativistic || p->precision != MCC_FP64 || p->pairing != MCC_PAIRING_ORDER_N ||
+      p->method == MCC_HARD_SPHERE)
     return MCC_ERR_UNSUPPORTED;
   HIP_TRY(hipSetDevice(ctx->device));
   if (!ensure_lists(ctx, ctx->lists, ctx->counts, n_cells)) return MCC_ERR_OOM;

@@ -92,6 +92,53 @@ __device__ __forceinline__ void scatter_pair_nr(double *vx, double *vy, double *
   }
 }
 
+// Hard-sphere pair (the non-Coulomb process of the collision integral of
+// Sec. 2 with the weighting of Sec. 3): s = sigma n_eff |u| dt is the
+// expected number of collisions in the step; the pair collides with
+// probability 1 - exp(-s) and then scatters isotropically (1 - cos chi
+// uniform on (0, 2)).  Words: x the collision, y the angle, z the azimuth,
+// w the heavier particle's acceptance.  FP64.
+__device__ __forceinline__ void scatter_pair_hs(double *vx, double *vy, double *vz,
+                                                const double *w, int I, int J, uint32_t kp,
+                                                double sigma_dt_f_nmin_dV, double fa, double fb,
+                                                uint32_t cell, uint32_t step_lo, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+  const double vix = vx[I], viy = vy[I], viz = vz[I];
+  const double vjx = vx[J], vjy = vy[J], vjz = vz[J];
+  const double wi = w[I], wj = w[J];
+  const double ux = vix - vjx, uy = viy - vjy, uz = viz - vjz;
+  const double um2 = ux * ux + uy * uy + uz * uz;
+  if (um2 == 0.0) return;
+  const double wmax = wi > wj ? wi : wj;
+  const double s = sigma_dt_f_nmin_dV * wmax * sqrt(um2);
+  if (!(s > 0.0)) return;
+  const U4 r = philox(kp, cell, step_lo, c3, k0, k1);
+  if (!(unif64(r.x) < -expm1(-s))) return;
+  const double oc = 2.0 * unif64(r.y);
+  const double st = sqrt(oc * (2.0 - oc));
+  double sp, cp;
+  KMath<double>::sincos2pi(unif64(r.z), sp, cp);
+  double dx, dy, dz;
+  rotate_delta<double>(ux, uy, uz, st, oc, sp, cp, dx, dy, dz);
+  const double u3 = unif64(r.w);
+  const double wratio = (wi < wj ? wi : wj) / wmax;
+  bool ai = true, aj = true;
+  if (wi < wj)
+    aj = u3 <= wratio;
+  else if (wj < wi)
+    ai = u3 <= wratio;
+  if (ai) {
+    vx[I] = vix + fa * dx;
+    vy[I] = viy + fa * dy;
+    vz[I] = viz + fa * dz;
+  }
+  if (aj) {
+    vx[J] = vjx - fb * dx;
+    vy[J] = vjy - fb * dy;
+    vz[J] = vjz - fb * dz;
+  }
+}
+
 // The FP64 pair kinematics as a call rather than inline: its transcendental
 // code then does not share a register allocation with the rest of the cell
 // kernel, which roughly halves the kernel's registers (measured: the FP64
@@ -100,8 +147,11 @@ __device__ __attribute__((noinline)) void scatter_pair_nr_f64(
     double *vx, double *vy, double *vz, const double *w, int I, int J, uint32_t kp,
     double coef_f_nmin_dV, double fa, double fb, int method, uint32_t cell, uint32_t step_lo,
     uint32_t c3, uint32_t k0, uint32_t k1, const double2 *n97tab) {
-  scatter_pair_nr<double>(vx, vy, vz, w, I, J, kp, coef_f_nmin_dV, fa, fb, method, cell, step_lo,
-                          c3, k0, k1, n97tab);
+  if (method == MCC_HARD_SPHERE)
+    scatter_pair_hs(vx, vy, vz, w, I, J, kp, coef_f_nmin_dV, fa, fb, cell, step_lo, c3, k0, k1);
+  else
+    scatter_pair_nr<double>(vx, vy, vz, w, I, J, kp, coef_f_nmin_dV, fa, fb, method, cell,
+                            step_lo, c3, k0, k1, n97tab);
 }
 
 // ---------------------------------------------------------------------------

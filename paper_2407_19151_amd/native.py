@@ -16,7 +16,7 @@ from typing import Optional, Sequence, Tuple
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcc_hip.so")
 
-MCC_TA77, MCC_N97 = 0, 1
+MCC_TA77, MCC_N97, MCC_HARD_SPHERE = 0, 1, 2
 MCC_FP64, MCC_FP32_KINEMATICS = 0, 1
 MCC_FAIL_RESET, MCC_FAIL_KEEP = 0, 1
 MCC_PAIRING_ORDER_N, MCC_PAIRING_NXN, MCC_PAIRING_DUPLICITY = 0, 1, 2
@@ -41,7 +41,7 @@ class mcc_species(C.Structure):
 
 
 class mcc_collision(C.Structure):
-    _fields_ = [("a", C.c_int32), ("b", C.c_int32)]
+    _fields_ = [("a", C.c_int32), ("b", C.c_int32), ("cross_section", C.c_double)]
 
 
 class mcc_params(C.Structure):
@@ -163,11 +163,14 @@ def _species(mass: Sequence[float], charge: Sequence[float]):
     return arr
 
 
-def _collisions(coll: Sequence[Tuple[int, int]]):
+def _collisions(coll: Sequence[Tuple]):
+    """(a, b) or (a, b, cross_section); the cross-section is read by the
+    hard-sphere method only."""
     arr = (mcc_collision * max(len(coll), 1))()
-    for i, (a, b) in enumerate(coll):
-        arr[i].a = int(a)
-        arr[i].b = int(b)
+    for i, c in enumerate(coll):
+        arr[i].a = int(c[0])
+        arr[i].b = int(c[1])
+        arr[i].cross_section = float(c[2]) if len(c) > 2 else 0.0
     return arr
 
 

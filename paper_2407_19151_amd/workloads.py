@@ -39,6 +39,7 @@ import numpy as np
 
 TA77 = 0
 N97 = 1
+HARD_SPHERE = 2   # elastic, isotropic, constant cross-section (collision tuples (a, b, sigma))
 
 PHILOX_SEED_BASE = 0x2407_1915_1000_0000
 
@@ -96,7 +97,8 @@ class Workload:
         in its cell)."""
         cnt = np.diff(self.offsets).reshape(self.n_cells, self.n_species)
         tot = 0
-        for a, b in self.collisions:
+        for c in self.collisions:
+            a, b = c[0], c[1]
             if a == b:
                 na = cnt[:, a]
                 tot += int(na[na >= 2].sum())
@@ -208,6 +210,27 @@ def config3(n_cells: int = 65536, seed_data: int = 3, method: int = N97) -> Work
                    method=method, seed_data=seed_data,
                    seed=PHILOX_SEED_BASE + 3, steps=20)
     return _scale_electron_density(wl)
+
+
+def hard_sphere(wl: Workload, collision_prob: float = 0.05) -> Workload:
+    """The same population under the hard-sphere process: collision (a, b)
+    gets the cross-section with which a particle of species a expects about
+    `collision_prob` collisions per step, at the mean density of species b
+    and the mean relative speed of two Maxwellians with the populations'
+    velocity variances (sqrt(8 / pi) g, g^2 the sum of the per-component
+    variances)."""
+    dV = np.broadcast_to(np.asarray(wl.cell_volume, dtype=np.float64), (wl.n_cells,))
+    var = [float((wl.vx[wl.species == s] ** 2 + wl.vy[wl.species == s] ** 2
+                  + wl.vz[wl.species == s] ** 2).mean()) / 3.0 for s in range(wl.n_species)]
+    coll = []
+    for c in wl.collisions:
+        a, b = c[0], c[1]
+        dens_b = float(np.bincount(wl.cells[wl.species == b], wl.w[wl.species == b],
+                                   wl.n_cells).sum() / dV.sum())
+        mean_u = math.sqrt(8.0 / math.pi) * math.sqrt(var[a] + var[b])
+        coll.append((a, b, collision_prob / (dens_b * mean_u * wl.dt)))
+    return dataclasses.replace(wl, name=wl.name + ", hard spheres", method=HARD_SPHERE,
+                               collisions=coll)
 
 
 def maxwell_juttner_speed(rng, theta: float, n: int) -> np.ndarray:
