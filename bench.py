@@ -296,6 +296,7 @@ def rebin_bench(steps, warmup):
     off = dev(wl.offsets)
     sp = dev(wl.species.astype(np.int32))
     pay = [dev(a) for a in (wl.w, wl.vx, wl.vy, wl.vz)]
+    pay_out = [torch.empty_like(t) for t in pay]
     rng = np.random.default_rng(5)
     cell = wl.cells.astype(np.int32)
 
@@ -321,18 +322,23 @@ def rebin_bench(steps, warmup):
         cn = dev(new.astype(np.int32))
         t_keys = timed(lambda: ctx.rebin(off, cn, wl.n_cells, wl.n_species))
         t_pay = timed(lambda: ctx.rebin(off, cn, wl.n_cells, wl.n_species, *pay))
+        t_out = timed(lambda: ctx.rebin_out(off, cn, wl.n_cells, wl.n_species, *pay, *pay_out))
         t_bin = timed(lambda: ctx.bin(cn, sp, wl.n_cells, wl.n_species))
         assert ctx.device_error() == 0
         print(json.dumps({
             "workload": "65536-cell population (%d particles), %.0f %% moved" % (n, 100 * frac),
-            "rebin_ms": t_keys, "rebin_with_payload_ms": t_pay, "bin_from_scratch_ms": t_bin,
+            "rebin_ms": t_keys, "rebin_with_payload_ms": t_pay,
+            "rebin_out_of_place_ms": t_out, "bin_from_scratch_ms": t_bin,
             "speedup_vs_bin": t_bin / t_keys,
             "roofline": {"bound": "hbm", "unit": "GB/s", "peak": 8000.0,
                          "keys": {"bytes_per_particle": 8, "achieved": 8 * n / t_keys / 1e6,
                                   "frac": 8 * n / t_keys / 1e6 / 8000.0},
                          "with_payload": {"bytes_per_particle": 72,
                                           "achieved": 72 * n / t_pay / 1e6,
-                                          "frac": 72 * n / t_pay / 1e6 / 8000.0}},
+                                          "frac": 72 * n / t_pay / 1e6 / 8000.0},
+                         "out_of_place": {"bytes_per_particle": 72,
+                                          "achieved": 72 * n / t_out / 1e6,
+                                          "frac": 72 * n / t_out / 1e6 / 8000.0}},
             "steps": steps}), flush=True)
 
 

@@ -303,6 +303,18 @@ mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells,
 mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
                      const int64_t *offsets, const int32_t *cells_new, int64_t *offsets_out,
                      int32_t *perm_out, double *weights, double *vx, double *vy, double *vz);
+/* The same regrouping with the payload gathered out of place, for callers
+ * that keep two sets of particle arrays and swap them: weights, vx, vy, vz
+ * (read) go to weights_out, vx_out, vy_out, vz_out (written) in the new
+ * order, with no scratch arrays and no copy back.  All eight are required
+ * when n > 0.  An output array must not overlap an input array (the same
+ * pointer is rejected with MCC_ERR_INVALID; partial overlap is not
+ * detected).  Other arguments and errors as for mcc_rebin. */
+mcc_status mcc_rebin_out(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                         const int64_t *offsets, const int32_t *cells_new, int64_t *offsets_out,
+                         int32_t *perm_out, const double *weights, const double *vx,
+                         const double *vy, const double *vz, double *weights_out,
+                         double *vx_out, double *vy_out, double *vz_out);
 
 /*
  * Batched form: a plan binds the sorted arrays of one particle population

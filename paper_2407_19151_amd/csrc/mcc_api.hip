@@ -608,14 +608,14 @@ mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int32_t 
   return finish(ctx);
 }
 
-mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
-                     const int64_t *offsets, const int32_t *cells_new, int64_t *offsets_out,
-                     int32_t *perm_out, double *weights, double *vx, double *vy, double *vz) {
+namespace {
+// the regrouping of mcc_rebin and mcc_rebin_out: offsets_out and perm_out
+mcc_status rebin_keys(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                      const int64_t *offsets, const int32_t *cells_new, int64_t *offsets_out,
+                      int32_t *perm_out) {
   if (!ctx || n < 0 || n_cells < 0 || n_species < 1 || n_species > MCC_MAX_SPECIES ||
       !offsets || !offsets_out || (n > 0 && (!cells_new || !perm_out)))
     return MCC_ERR_INVALID;
-  const int any = (weights != nullptr) + (vx != nullptr) + (vy != nullptr) + (vz != nullptr);
-  if (any != 0 && any != 4) return MCC_ERR_INVALID;
   const int64_t m = (int64_t)n_cells * n_species;
   if (n > (int64_t)INT32_MAX || m > (int64_t)INT32_MAX) return MCC_ERR_UNSUPPORTED;
   if (m == 0 && n > 0) return MCC_ERR_INVALID;
@@ -633,7 +633,7 @@ mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species
     return MCC_ERR_OOM;
   if (m == 0) {
     HIP_TRY(launch_set_u64(reinterpret_cast<uint64_t *>(offsets_out), 0ull, ctx->stream));
-    return finish(ctx);
+    return MCC_OK;
   }
   HIP_TRY(launch_rebin(n, m, n_species, n_cells, offsets, cells_new, offsets_out, perm_out,
                        ctx->rb_gold.as<int32_t>(), ctx->rb_gnew.as<int32_t>(),
@@ -642,7 +642,20 @@ mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species
                        ctx->rb_arrive.as<uint32_t>(), ctx->rb_acur.as<uint32_t>(),
                        ctx->rb_cnt.as<uint32_t>(), ctx->rb_aoff.as<int64_t>(), ctx->rb_rec.p,
                        ctx->tiles.as<int64_t>(), ctx->err, ctx->stream));
-  if (any && n > 0) {
+  return MCC_OK;
+}
+}  // namespace
+
+mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                     const int64_t *offsets, const int32_t *cells_new, int64_t *offsets_out,
+                     int32_t *perm_out, double *weights, double *vx, double *vy, double *vz) {
+  const int any = (weights != nullptr) + (vx != nullptr) + (vy != nullptr) + (vz != nullptr);
+  if (any != 0 && any != 4) return MCC_ERR_INVALID;
+  const mcc_status st =
+      rebin_keys(ctx, n, n_cells, n_species, offsets, cells_new, offsets_out, perm_out);
+  if (st != MCC_OK) return st;
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  if (any && n > 0 && (int64_t)n_cells * n_species > 0) {
     if (!ctx->gw.ensure(sizeof(double) * nn) || !ctx->gx.ensure(sizeof(double) * nn) ||
         !ctx->gy.ensure(sizeof(double) * nn) || !ctx->gz.ensure(sizeof(double) * nn))
       return MCC_ERR_OOM;
@@ -655,6 +668,27 @@ mcc_status mcc_rebin(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species
     HIP_TRY(hipMemcpyAsync(vy, ctx->gy.p, b, hipMemcpyDeviceToDevice, ctx->stream));
     HIP_TRY(hipMemcpyAsync(vz, ctx->gz.p, b, hipMemcpyDeviceToDevice, ctx->stream));
   }
+  return finish(ctx);
+}
+
+mcc_status mcc_rebin_out(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                         const int64_t *offsets, const int32_t *cells_new, int64_t *offsets_out,
+                         int32_t *perm_out, const double *weights, const double *vx,
+                         const double *vy, const double *vz, double *weights_out,
+                         double *vx_out, double *vy_out, double *vz_out) {
+  if (n > 0 && (!weights || !vx || !vy || !vz || !weights_out || !vx_out || !vy_out || !vz_out))
+    return MCC_ERR_INVALID;
+  const double *in[4] = {weights, vx, vy, vz};
+  const double *out[4] = {weights_out, vx_out, vy_out, vz_out};
+  for (int i = 0; i < 4 && n > 0; ++i)
+    for (int j = 0; j < 4; ++j)
+      if (in[i] == out[j]) return MCC_ERR_INVALID;  // a gather cannot run in place
+  const mcc_status st =
+      rebin_keys(ctx, n, n_cells, n_species, offsets, cells_new, offsets_out, perm_out);
+  if (st != MCC_OK) return st;
+  if (n > 0 && (int64_t)n_cells * n_species > 0)
+    HIP_TRY(launch_gather(n, perm_out, weights, vx, vy, vz, weights_out, vx_out, vy_out, vz_out,
+                          ctx->stream));
   return finish(ctx);
 }
 

@@ -31,7 +31,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "device out of memory",
 EXPORTS = ["mcc_default_params", "mcc_status_string", "mcc_create", "mcc_set_stream",
            "mcc_set_variant",
            "mcc_destroy", "mcc_device_error", "mcc_collide_sorted", "mcc_collide",
-           "mcc_bin", "mcc_rebin", "mcc_plan_create", "mcc_plan_run", "mcc_plan_describe",
+           "mcc_bin", "mcc_rebin", "mcc_rebin_out", "mcc_plan_create", "mcc_plan_run",
+           "mcc_plan_describe",
            "mcc_plan_destroy", "mcc_sample_angles", "mcc_plan_run_bucket",
            "mcc_collide_sorted_jvp"]
 
@@ -109,6 +110,8 @@ def load(path: str = LIB_PATH):
     L.mcc_bin.argtypes = [P, i64, P, P, i32, i32, P, P]
     L.mcc_rebin.argtypes = [P, i64, i32, i32, P, P, P, P, P, P, P, P]
     L.mcc_rebin.restype = C.c_int
+    L.mcc_rebin_out.argtypes = [P, i64, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P]
+    L.mcc_rebin_out.restype = C.c_int
     L.mcc_bin.restype = C.c_int
     L.mcc_plan_create.argtypes = [P, C.POINTER(P), i64, i32, i32, P, P, P, P, P, P, f64,
                                   C.POINTER(mcc_species), i32, C.POINTER(mcc_collision), f64,
@@ -367,6 +370,25 @@ class Context:
         _check("mcc_rebin", self.L.mcc_rebin(self.h, n, n_cells, n_species, _ptr(offsets),
                                              _ptr(cells_new), _ptr(off), _ptr(perm),
                                              *(_ptr(a) for a in pay)))
+        return off, perm[:n]
+
+    def rebin_out(self, offsets, cells_new, n_cells: int, n_species: int, w, vx, vy, vz,
+                  w_out, vx_out, vy_out, vz_out):
+        """mcc_rebin_out: (offsets_new, perm) on the device; w, vx, vy, vz are
+        gathered into w_out, vx_out, vy_out, vz_out in the new order."""
+        import torch
+        n = cells_new.numel()
+        _expect(cells_new, torch.int32, n, "cells_new")
+        _expect(offsets, torch.int64, n_cells * n_species + 1, "offsets")
+        pay = (w, vx, vy, vz, w_out, vx_out, vy_out, vz_out)
+        for a, name in zip(pay, ("w", "vx", "vy", "vz", "w_out", "vx_out", "vy_out", "vz_out")):
+            _expect(a, torch.float64, n, name)
+        off = torch.empty(n_cells * n_species + 1, dtype=torch.int64, device=cells_new.device)
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=cells_new.device)
+        self._stream()
+        _check("mcc_rebin_out", self.L.mcc_rebin_out(self.h, n, n_cells, n_species,
+                                                     _ptr(offsets), _ptr(cells_new), _ptr(off),
+                                                     _ptr(perm), *(_ptr(a) for a in pay)))
         return off, perm[:n]
 
 

@@ -5,7 +5,9 @@ After a push, the particle at grouped position p goes to cell cells_new[p]
 current order from scratch gives: offsets by (cell, species) and, inside
 every group, ascending current position.  The oracle's counting sort is
 that definition; offsets and permutation are compared bit for bit, and the
-payload must come out as the old arrays gathered through the permutation.
+payload must come out as the old arrays gathered through the permutation,
+in place (mcc_rebin) and into separate output arrays (mcc_rebin_out, which
+must leave its inputs untouched).
 Cases: no movers, neighbour moves at several rates, far jumps, every
 particle moving, emptied and newly filled groups, one cell, three species,
 no particles, and cell ids out of range (reported; such particles stay).
@@ -70,6 +72,17 @@ def _check(ctx, off, sp, cells_new, n_cells, S, expect_err=0, keep=None):
     assert np.array_equal(perm.cpu().numpy().astype(np.int64), ref_perm)
     for a, t in zip(pay, tp):
         assert np.array_equal(t.cpu().numpy(), a[ref_perm])
+    # out of place, from the original payload
+    tin = [dev(a) for a in pay]
+    tout = [torch.full_like(t, np.nan) for t in tin]
+    off2, perm2 = ctx.rebin_out(dev(off), dev(cells_new), n_cells, S, *tin, *tout)
+    torch.cuda.synchronize()
+    assert ctx.device_error() == expect_err
+    assert np.array_equal(off2.cpu().numpy(), ref_off)
+    assert np.array_equal(perm2.cpu().numpy().astype(np.int64), ref_perm)
+    for a, ti, to in zip(pay, tin, tout):
+        assert np.array_equal(ti.cpu().numpy(), a)
+        assert np.array_equal(to.cpu().numpy(), a[ref_perm])
 
 
 @pytest.mark.parametrize("frac", [0.0, 0.01, 0.05, 0.3, 1.0])
@@ -113,6 +126,20 @@ def test_rebin_cell_out_of_range_is_reported_and_kept(ctx):
     keep = new.copy()
     keep[bad] = cell[bad]
     _check(ctx, off, sp, new, n_cells, S, expect_err=3, keep=keep)
+
+
+def test_rebin_out_rejects_an_output_that_is_an_input(ctx):
+    import torch
+    from paper_2407_19151_amd import native
+    rng = np.random.default_rng(12)
+    off, cell, sp = _population(rng, 10, 2, 5, empty_frac=0.0)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tin = [dev(rng.normal(size=cell.size)) for _ in range(4)]
+    tout = [torch.empty_like(t) for t in tin]
+    tout[2] = tin[0]
+    with pytest.raises(native.MCCError) as e:
+        ctx.rebin_out(dev(off), dev(cell), 10, 2, *tin, *tout)
+    assert e.value.code == -1
 
 
 def test_rebin_full_size_population(ctx):
