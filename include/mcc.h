@@ -5,9 +5,11 @@
  * Method: J. R. Angus, Y. Fu, V. Geyko, D. Grote, D. Larson,
  * "Moment-preserving Monte-Carlo Coulomb collision method for particle codes"
  * (arXiv 2407.19151).  One call applies one time step of the paper's
- * Algorithm 1 to every cell: random binary pairing (Fig. 1, Sec. 3.2),
- * weighted TA77/N97 scatter with w_min/w_max acceptance (Eq. (12),
- * Secs. 3.1-3.2), momentum restore (Eq. (17)), energy-violation partition
+ * Algorithm 1 to every cell: random binary pairing (Fig. 1, Sec. 3.2; or
+ * N x N, Sec. 3.1; or Higginson et al.'s duplicity), weighted TA77/N97
+ * scatter with w_min/w_max acceptance (Eq. (12), Secs. 3.1-3.2; or the
+ * hard-sphere process, a non-Coulomb case of Sec. 2), momentum restore
+ * (Eq. (17)), energy-violation partition
  * (Eqs. (18), (24)) and zero-angle inelastic pair energy correction
  * (Eqs. (19)-(23)); relativistic variant of Appendix A; failure fallback of
  * Sec. 6.2.
