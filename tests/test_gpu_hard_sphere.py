@@ -190,3 +190,37 @@ def test_hs_full_population_sampled_cells_and_conservation(ctx):
     info = check_parity(sub, vg[:, idx], ref.velocities(), sub.velocities(), tol=FP64_TOL,
                         rerun=rerun)
     print("  %d sampled cells (%d particles): %s" % (cells.size, idx.size, info), flush=True)
+
+
+def test_hs_maxwellian_energy_exchange_at_scale(ctx):
+    """Independent of the oracle: 20 000 cells of 32 + 16 particles (masses 1
+    and 4, T 2 and 1, equal densities), inter-species hard spheres at about
+    3 % collision probability per particle.  One GPU step moves the energy
+    of species a at the textbook rate d(3 T_a / 2)/dt = -n_b sigma (mu / M)
+    8 sqrt(2 / pi) g (T_a - T_b), g^2 = T_a / m_a + T_b / m_b, within 3 %
+    plus four standard errors of the per-cell gains."""
+    from paper_2407_19151_amd import native
+    n_cells, na, nb = 20000, 32, 16
+    base = custom_workload([(na, nb)] * n_cells, seed=49, masses=(1.0, 4.0),
+                           collisions=((0, 1),), weight_mode="equal")
+    base.w[base.species == 1] *= na / nb          # equal densities
+    wl = W.hard_sphere(base, 0.03)
+    sigma = wl.collisions[0][2]
+    v0 = wl.velocities().copy()
+    vg, _, _ = _gpu_step(ctx, wl, 0, moment_correction=False, precision=native.MCC_FP64)
+    ma, mb = wl.mass
+    a = wl.species == 0
+    ta = ma * (v0[:, a] ** 2).sum() / (3 * a.sum())
+    tb = mb * (v0[:, ~a] ** 2).sum() / (3 * (~a).sum())
+    dV = float(np.mean(wl.cell_volume))
+    n_b = wl.w[~a].sum() / (n_cells * dV)
+    g = math.sqrt(ta / ma + tb / mb)
+    want = -n_b * sigma * (ma * mb / (ma + mb) ** 2) * 8 * math.sqrt(2 / math.pi) * g \
+        * (ta - tb) * wl.dt
+    e = lambda v: (0.5 * ma * (v[:, a] ** 2).sum(0)).reshape(n_cells, na).sum(1)
+    gain = (e(vg) - e(v0)) / na
+    se = gain.std() / math.sqrt(n_cells)
+    print("energy gain per a particle %.4e +- %.1e, hard-sphere rate x dt %.4e"
+          % (gain.mean(), se, want), flush=True)
+    assert abs(gain.mean() - want) < 0.03 * abs(want) + 4 * se
+    assert 4 * se < 0.15 * abs(want)
