@@ -633,7 +633,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   constexpr bool DUAL = !TAN && !REL && !DIAG && PAIRING == PAIR_ORDER_N;
   static_assert(PAIRING == PAIR_ORDER_N || !(TAN || DIAG),
                 "the N x N and duplicity pairings have no tangent or diagnostic form");
-  static_assert(!GL || TPC == WAVE, "the global layout runs one wave per cell");
+  static_assert(!GL || TPC <= 512, "the global layout runs at most 8 waves per cell");
   static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT && !DIAG),
                 "the tangent form is FP64 non-relativistic, without diagnostics");
   __shared__ double red[2 * 6 * NW];

@@ -7,7 +7,7 @@ namespace mcc {
   ((const void *)&collide_kernel<variant_of(MODE_FP64, i).tpc, variant_of(MODE_FP64, i).cap, \
                                  double, false, variant_of(MODE_FP64, i).layout>)
 const void *const kTable_FP64[NVARIANT] = {V(0), V(1), V(2),  V(3),  V(4),  V(5),  V(6),
-                                    V(7), V(8), V(9), V(10), V(11), V(12), V(13)};
+                                    V(7), V(8), V(9), V(10), V(11), V(12), V(13), V(14), V(15)};
 #undef V
 }  // namespace mcc
 

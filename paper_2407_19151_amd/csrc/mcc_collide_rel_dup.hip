@@ -8,7 +8,7 @@ namespace mcc {
                                  variant_of(MODE_REL_DUP, i).cap, double, true, \
                                  variant_of(MODE_REL_DUP, i).layout, false, false, PAIR_DUPLICITY>)
 const void *const kTable_REL_DUP[NVARIANT] = {V(0), V(1), V(2),  V(3),  V(4),  V(5),  V(6),
-                                             V(7), V(8), V(9), V(10), V(11), V(12), V(13)};
+                                             V(7), V(8), V(9), V(10), V(11), V(12), V(13), V(14), V(15)};
 #undef V
 }  // namespace mcc
 

@@ -37,18 +37,23 @@ inline constexpr int base_mode(int mode) {
 }
 
 // layout: 0 all in LDS; 1 compact LDS (weights read from the input);
-// 2 per-workgroup global scratch with one wave per cell
+// 2 per-workgroup global scratch (one wave per cell, or several waves for
+// the plain FP64 and FP32 modes)
 struct Variant {
   int tpc;     // threads per cell (workgroup size)
   int cap;     // largest cell the variant holds
   int layout;  // 0 LDS, 1 compact LDS, 2 global scratch
 };
 
-constexpr int NVARIANT = 14;
+constexpr int NVARIANT = 16;
 constexpr Variant kVariants[NVARIANT] = {
     {64, 128, 0},    {64, 256, 0},   {128, 256, 0},  {128, 512, 0},  {256, 512, 0},
     {256, 1024, 0},  {512, 1024, 0}, {512, 2048, 0}, {1024, 2048, 0}, {1024, 4096, 1},
-    {64, 32768, 2},  {256, 2048, 0}, {512, 4096, 1}, {256, 4096, 1}};
+    {64, 32768, 2},  {256, 2048, 0}, {512, 4096, 1}, {256, 4096, 1},
+    {256, 32768, 2}, {512, 32768, 2}};
+// the one-wave global variant, which the modes without multi-wave global
+// kernels use in place of variants 14 and 15
+constexpr int kGlobalOneWave = 10;
 // the relativistic mode keeps a per-pair h(-mu) buffer, which the compact
 // layout has no room for: its 4096-cell variants use global scratch
 constexpr Variant kRelVariant4096 = {64, 4096, 2};
@@ -58,13 +63,15 @@ constexpr int NBUCKET = 7;
 constexpr int kBucketCap[NBUCKET] = {128, 256, 512, 1024, 2048, 4096, 32768};
 // default variant per bucket (the fastest measured on lognormal cell-size
 // mixes; the autotuner may pick another candidate): FP32 kinematics take 256
-// threads for the 2048 bucket, FP64 (more registers per thread) 512
-constexpr int kDefaultVariant[NBUCKET] = {0, 1, 3, 5, 7, 12, 10};
-constexpr int kDefaultVariantFP32[NBUCKET] = {0, 1, 3, 5, 11, 12, 10};
+// threads for the 2048 bucket, FP64 (more registers per thread) 512.  Cells
+// above 4096 particles take 8 waves in global scratch (measured on cells of
+// 4 400 to 8 200 particles: 5.1-5.3x the one-wave variant, 1.5x the 4-wave)
+constexpr int kDefaultVariant[NBUCKET] = {0, 1, 3, 5, 7, 12, 15};
+constexpr int kDefaultVariantFP32[NBUCKET] = {0, 1, 3, 5, 11, 12, 15};
 // candidates the autotuner times per bucket (-1 terminated)
 constexpr int kCandidates[NBUCKET][5] = {
     {0, 1, 2, -1, -1}, {1, 2, 3, 4, -1}, {3, 4, 5, 6, -1}, {5, 6, 7, 11, -1},
-    {7, 11, 8, -1, -1}, {12, 13, 9, -1, -1}, {10, -1, -1, -1, -1}};
+    {7, 11, 8, -1, -1}, {12, 13, 9, -1, -1}, {15, 14, 10, -1, -1}};
 
 // the tangent form keeps six more doubles per particle and one per pair: in
 // LDS up to 1024 particles, above that in global scratch
@@ -83,9 +90,15 @@ inline constexpr int default_variant(int mode, int bucket) {
                                                                     : kDefaultVariant[bucket];
 }
 
+// multi-wave global-scratch kernels: the plain FP64 and FP32 order-N modes
+// (the waves of a workgroup share their CU's L1, so the barrier orders their
+// scratch accesses as it does for LDS)
+inline constexpr bool multiwave_global(int m) { return m == MODE_FP64 || m == MODE_FP32; }
 inline constexpr Variant variant_of(int m, int v) {
   const int mode = base_mode(m);
-  return ((mode == MODE_REL || mode == MODE_REL_DIAG) && kVariants[v].layout == 1)
+  return (kVariants[v].layout == 2 && kVariants[v].tpc > 64 && !multiwave_global(m))
+             ? variant_of(m, kGlobalOneWave)
+         : ((mode == MODE_REL || mode == MODE_REL_DIAG) && kVariants[v].layout == 1)
              ? kRelVariant4096
          : (mode == MODE_TAN && kVariants[v].cap > 1024 && kVariants[v].layout != 2)
              ? kTanVariantBig

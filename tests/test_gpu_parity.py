@@ -293,7 +293,7 @@ def test_plan_graph_replay_equals_plain_steps(ctx):
 
 VARIANTS = [(64, 128), (64, 256), (128, 256), (128, 512), (256, 512), (256, 1024),
             (512, 1024), (512, 2048), (1024, 2048), (1024, 4096), (64, 32768), (256, 2048),
-            (512, 4096), (256, 4096)]
+            (512, 4096), (256, 4096), (256, 32768), (512, 32768)]
 BUCKET_CAP = [128, 256, 512, 1024, 2048, 4096, 32768]
 
 

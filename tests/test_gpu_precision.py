@@ -109,3 +109,33 @@ def test_fp32_relaxation_rate_matches_fp64_oracle(ctx):
     assert abs(r["fp64"] / r["oracle"] - 1) < 1e-9
     assert d32 < 1e-3
     assert err32 < 1e-3
+
+
+def test_fp32_kinematics_global_layout_waves_agree(ctx):
+    """Cells above 4096 particles in global scratch with FP32 kinematics: the
+    4- and 8-wave variants against the one-wave variant, element by element.
+    Per pair they do the same arithmetic; only the order of the FP64 sums of
+    the momentum restore and the correction differs, so a difference beyond
+    rounding would be a fault of the multi-wave form.  (The FP64 forms of all
+    three match the oracle in the every-variant test.)"""
+    from paper_2407_19151_amd import native, runner
+    from gpu_helpers import custom_workload
+    sizes = [(2300, 2800), (4000, 3000), (100, 5000), (60, 40)]
+    wl = custom_workload(sizes, seed=61)
+    v0 = wl.velocities().copy()
+    out = {}
+    for variant in (10, 14, 15):
+        dw = runner.DeviceWorkload(wl)
+        try:
+            ctx.set_variant(6, variant)
+            runner.collide_sorted(ctx, dw, 2, params=runner.params_for(
+                wl, precision=native.MCC_FP32_KINEMATICS))
+            out[variant] = (dw.velocities(), native.read_stats(dw.stats))
+        finally:
+            ctx.set_variant(6, -1)
+        assert ctx.device_error() == 0
+    for variant in (14, 15):
+        info = check_parity(wl, out[variant][0], out[10][0], v0, tol=1e-5, cond_tol=1e-3)
+        print("fp32, %d waves against one: %s" % (4 if variant == 14 else 8, info), flush=True)
+        for k in ("pairs", "collisions", "failed"):
+            assert out[variant][1][k] == out[10][1][k]
