@@ -240,3 +240,28 @@ def test_order_n_and_nxn_relaxation_differ_by_the_finite_s_factor(ctx):
               flush=True)
         assert out[NXN] > 0.25
         assert abs(got / want - 1) < 0.08
+
+
+@pytest.mark.parametrize("pairing", [NXN, 2])
+def test_global_layout_waves_agree_fp32(ctx, pairing):
+    """N x N and duplicity pairing on a cell above 4096 particles with FP32
+    kinematics: the 8-wave global kernel against the one-wave one, element by
+    element (their FP64 forms match the oracle in the large-cell tests).  The
+    step is the well-conditioned small one, so only the order of the FP64
+    sums may differ."""
+    from paper_2407_19151_amd import native
+    sizes = [(2500, 2000), (30, 20)]
+    wl = custom_workload(sizes, seed=50 + pairing, dt=DT_SMALL)
+    v0 = wl.velocities().copy()
+    out = {}
+    for variant in (10, 15):
+        try:
+            ctx.set_variant(6, variant)
+            out[variant] = _gpu_step(ctx, wl, 1, pairing=pairing,
+                                     precision=native.MCC_FP32_KINEMATICS)
+        finally:
+            ctx.set_variant(6, -1)
+    info = check_parity(wl, out[15][0], out[10][0], v0, tol=1e-5, cond_tol=1e-3)
+    print("pairing %d fp32, 8 waves against one: %s" % (pairing, info), flush=True)
+    for k in ("pairs", "collisions", "failed"):
+        assert out[15][1][k] == out[10][1][k]
