@@ -90,12 +90,13 @@ inline constexpr int default_variant(int mode, int bucket) {
                                                                     : kDefaultVariant[bucket];
 }
 
-// multi-wave global-scratch kernels: the plain FP64 and FP32 modes of every
-// pairing (the waves of a workgroup share their CU's L1, so the barrier
-// orders their scratch accesses as it does for LDS)
+// multi-wave global-scratch kernels: the FP64, FP32 and relativistic modes
+// of every pairing (the waves of a workgroup share their CU's L1, so the
+// barrier orders their scratch accesses as it does for LDS)
 inline constexpr bool multiwave_global(int m) {
-  return m == MODE_FP64 || m == MODE_FP32 || m == MODE_FP64_NXN || m == MODE_FP32_NXN ||
-         m == MODE_FP64_DUP || m == MODE_FP32_DUP;
+  return m == MODE_FP64 || m == MODE_FP32 || m == MODE_REL || m == MODE_FP64_NXN ||
+         m == MODE_FP32_NXN || m == MODE_REL_NXN || m == MODE_FP64_DUP || m == MODE_FP32_DUP ||
+         m == MODE_REL_DUP;
 }
 inline constexpr Variant variant_of(int m, int v) {
   const int mode = base_mode(m);

@@ -225,6 +225,19 @@ def test_parity_relativistic_subset(ctx):
     _parity(ctx, wl2, 1)
 
 
+def test_parity_relativistic_global_layout(ctx):
+    """Relativistic cells in global scratch: 2048 to 4096 particles (one
+    wave) and above 4096 (8 waves by default, one wave forced)."""
+    wl = custom_workload([(1500, 1200), (3000, 2500), (60, 40)], seed=9, masses=(1.0, 1836.0),
+                         relativistic=True, c=1.0, dt=0.003)
+    _parity(ctx, wl.copy(), 1)
+    try:
+        ctx.set_variant(6, 10)
+        _parity(ctx, wl.copy(), 1)
+    finally:
+        ctx.set_variant(6, -1)
+
+
 def test_diagnostics_show_roundoff_conservation(ctx):
     wl = W.config2(n_cells=32)
     _, sg, so = _parity(ctx, wl, 0, diagnostics=True)
