@@ -57,6 +57,9 @@ constexpr int kGlobalOneWave = 10;
 // the relativistic mode keeps a per-pair h(-mu) buffer, which the compact
 // layout has no room for: its 4096-cell variants use global scratch
 constexpr Variant kRelVariant4096 = {64, 4096, 2};
+// the same with 4 waves per cell, for the relativistic order-N step (8 waves
+// would cap the registers at 256 and spill)
+constexpr Variant kRelVariant4096Wide = {256, 4096, 2};
 
 // cell-size buckets: bucket b holds cells with kBucketCap[b-1] < n <= kBucketCap[b]
 constexpr int NBUCKET = 7;
@@ -103,7 +106,7 @@ inline constexpr Variant variant_of(int m, int v) {
   return (kVariants[v].layout == 2 && kVariants[v].tpc > 64 && !multiwave_global(m))
              ? variant_of(m, kGlobalOneWave)
          : ((mode == MODE_REL || mode == MODE_REL_DIAG) && kVariants[v].layout == 1)
-             ? kRelVariant4096
+             ? (m == MODE_REL ? kRelVariant4096Wide : kRelVariant4096)
          : (mode == MODE_TAN && kVariants[v].cap > 1024 && kVariants[v].layout != 2)
              ? kTanVariantBig
          : (mode == MODE_FP64 || mode == MODE_FP32 || mode == MODE_FP64_DIAG ||
