@@ -244,6 +244,21 @@ def test_diagnostics_show_roundoff_conservation(ctx):
     assert sg["max_rel_dP"] < 1e-14 and sg["max_rel_dE"] < 1e-14
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_diagnostics_on_cells_in_global_scratch(ctx, prec):
+    """Diagnostics on cells above 4096 particles (one-wave global kernel):
+    FP64 against the oracle; FP32 kinematics against the FP64 residual bar
+    (the correction is FP64 in both forms)."""
+    from paper_2407_19151_amd import native
+    wl = custom_workload([(3000, 2500), (60, 40)], seed=12)
+    if prec == 0:
+        _, sg, so = _parity(ctx, wl, 1, diagnostics=True)
+    else:
+        _, sg, _ = _gpu_step(ctx, wl, 1, diagnostics=True,
+                             precision=native.MCC_FP32_KINEMATICS)
+    assert sg["max_rel_dP"] < 1e-14 and sg["max_rel_dE"] < 1e-14
+
+
 def test_unsorted_entry_matches_oracle(ctx):
     from paper_2407_19151_amd import native, runner
     base = W.config2(n_cells=40)
