@@ -171,8 +171,9 @@ mcc_status mcc_device_error(mcc_ctx *ctx, int32_t *code);
  * capacity) table: 0 (64,128), 1 (64,256), 2 (128,256), 3 (128,512),
  * 4 (256,512), 5 (256,1024), 6 (512,1024), 7 (512,2048), 8 (1024,2048),
  * 9 (1024,4096), 10 (64,32768, one wave with global scratch), 11 (256,2048),
- * 12 (512,4096), 13 (256,4096); in relativistic mode 9, 12 and 13 run as
- * (64,4096) with global scratch.  -1 restores the default, which depends on
+ * 12 (512,4096), 13 (256,4096).  In relativistic mode 9, 12 and 13 run in
+ * global scratch: as (256,4096), four waves, in the order-N step, and as
+ * (64,4096), one wave, in its diagnostic, N x N and duplicity forms.  -1 restores the default, which depends on
  * the precision mode (built-in table, the fastest measured on lognormal
  * cell-size mixes).  The variant's capacity must hold the bucket's largest cell,
  * else MCC_ERR_INVALID.  Results agree between variants to rounding (the
@@ -329,7 +330,14 @@ mcc_status mcc_rebin_out(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_spe
  * moment correction on, it also computes once what depends on the weights
  * alone (per cell and species: sum w, sum w^2, the weight range, and the
  * descending-weight order of Algorithm 1), owning 40 B per (cell, species)
- * and 2 B per particle of device memory for it.
+ * and 2 B per particle of device memory for it.  A plan whose cells need the
+ * large-cell kernels (above 4096 particles, or above 2048 in relativistic
+ * mode) owns their global scratch too, 2.75 MB per compute unit for cells
+ * above 4096 particles (0.34 MB up to 4096), held until mcc_plan_destroy:
+ * its graph replays against that scratch, so later calls on the context
+ * (which grow the context's own scratch) never move it.  A plan shares the
+ * context's cell-queue counters and error word, so its replays must not
+ * overlap other work of the same context either.
  */
 mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n,
                            int32_t n_cells, int32_t n_species,

@@ -35,8 +35,8 @@ def build(force: bool = False) -> str:
             os.path.getmtime(LIB_PATH) < os.path.getmtime(_SRC)):
         tmp = LIB_PATH + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-std=gnu11", "-O2", "-ffp-contract=off",
-                               "-fno-fast-math", "-fPIC", "-shared", "-o", tmp,
-                               _SRC, "-lm"])
+                               "-fno-fast-math", "-fopenmp", "-fPIC", "-shared", "-o",
+                               tmp, _SRC, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 
@@ -74,11 +74,11 @@ def lib():
         L.oracle_scatter_pair.restype = None
         L.oracle_collide_sorted.argtypes = (
             [i64, i32, i32, P, P, P, i32, P, P, P, P, P, P, P, f64, f64, f64, u64, u64,
-             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, i32, P, P, P, P])
+             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, i32, P, P, P, P, i32])
         L.oracle_collide_sorted.restype = C.c_int
         L.oracle_collide.argtypes = (
             [i64, P, P, i32, i32, P, P, i32, P, P, P, P, P, P, P, f64, f64, f64, u64, u64,
-             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, P, P, P])
+             i32, i32, i32, i32, i32, i32, i32, f64, f64, f64, P, P, P, P, i32])
         L.oracle_collide.restype = C.c_int
         L.oracle_collide_sorted_traced.argtypes = (
             [i64, i32, i32, P, P, P, i32, P, P, P, P, P, P, f64, f64, f64, u64, u64,
@@ -86,8 +86,17 @@ def lib():
         L.oracle_collide_sorted_traced.restype = C.c_int
         L.oracle_bin.argtypes = [i64, P, P, i32, i32, P, P]
         L.oracle_bin.restype = C.c_int
+        L.oracle_set_threads.argtypes = [i32]
+        L.oracle_set_threads.restype = None
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's cell loop (default 1).  Cells are independent
+    and every random number is keyed by its cell, so results are the same,
+    bit for bit, for every thread count."""
+    lib().oracle_set_threads(int(n))
 
 
 def _p(a: Optional[np.ndarray]):
@@ -191,13 +200,16 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
                    keep_on_fail=False, f_E=0.05, eps0=1.0, c=math.inf,
                    cell_volume=1.0, cells: Optional[Sequence[int]] = None,
                    n_cells: Optional[int] = None, pairing: int = ORDER_N,
-                   cross_section=None) -> dict:
+                   cross_section=None, uniform23: bool = False) -> dict:
     """One step on (cell, species)-grouped arrays; vx, vy, vz updated in place.
     pairing: ORDER_N (Sec. 3.2), NXN (every pair once, Sec. 3.1) or
     DUPLICITY (order-N pairs, inter-species s with N_max / D, the variant the
     paper attributes to Higginson et al.).
     method HARD_SPHERE needs cross_section (one per collision, or a scalar):
-    charges, coulomb_log and eps0 are then unused."""
+    charges, coulomb_log and eps0 are then unused.
+    uniform23: draw the angle, Box-Muller phase and azimuth uniforms from the
+    top 23 bits of their words, (k + 1/2) 2^-23, as the FP32-kinematics form
+    does (the acceptance keeps the 32-bit uniform)."""
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     mass = _f64(mass)
     charge = _f64(charge)
@@ -223,7 +235,8 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
         _p(ca), _p(cb), _p(w), _p(vx), _p(vy), _p(vz), _p(cv), cvs, dt, coulomb_log,
         seed, step, method, int(pairing), int(relativistic), int(correction),
         int(sort_by_weight), max_passes, int(keep_on_fail), f_E, eps0, c, _p(cl),
-        0 if cl is None else cl.shape[0], _p(counters), _p(diag), _p(ccp), _p(sg))
+        0 if cl is None else cl.shape[0], _p(counters), _p(diag), _p(ccp), _p(sg),
+        int(uniform23))
     if rc != 0:
         raise OracleError("oracle_collide_sorted returned %d" % rc)
     return dict(pairs=int(counters[0]), corr_pairs=int(counters[1]),
@@ -235,7 +248,8 @@ def collide_sorted(offsets, mass, charge, collisions, w, vx, vy, vz, *, dt,
 def collide(cells, species, n_cells, mass, charge, collisions, w, vx, vy, vz, *, dt,
             coulomb_log, seed, step, method=N97, relativistic=False, correction=True,
             sort_by_weight=True, max_passes=1, keep_on_fail=False, f_E=0.05, eps0=1.0,
-            c=math.inf, cell_volume=1.0, pairing: int = ORDER_N, cross_section=None) -> dict:
+            c=math.inf, cell_volume=1.0, pairing: int = ORDER_N, cross_section=None,
+            uniform23: bool = False) -> dict:
     """One step on particles in any order; vx, vy, vz updated in place."""
     cells = np.ascontiguousarray(cells, dtype=np.int32)
     species = np.ascontiguousarray(species, dtype=np.int32)
@@ -258,7 +272,7 @@ def collide(cells, species, n_cells, mass, charge, collisions, w, vx, vy, vz, *,
         len(collisions), _p(ca), _p(cb), _p(w), _p(vx), _p(vy), _p(vz), _p(cv), cvs,
         dt, coulomb_log, seed, step, method, int(pairing), int(relativistic),
         int(correction), int(sort_by_weight), max_passes, int(keep_on_fail), f_E, eps0, c,
-        _p(counters), _p(diag), _p(ccp), _p(sg))
+        _p(counters), _p(diag), _p(ccp), _p(sg), int(uniform23))
     if rc != 0:
         raise OracleError("oracle_collide returned %d" % rc)
     return dict(pairs=int(counters[0]), corr_pairs=int(counters[1]),

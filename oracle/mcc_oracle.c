@@ -134,6 +134,13 @@ static void draw4(uint64_t seed, uint32_t c0, uint32_t cell, uint64_t step,
 /* uniform in (0,1): (a + 1/2) * 2^-32, exact in FP64 */
 static double unif(uint32_t a) { return ((double)a + 0.5) * 0x1p-32; }
 
+/* The FP32-kinematics form's uniform (reading of the design notes): the top
+ * 23 bits of the word, (k + 1/2) * 2^-23, which FP32 holds exactly and which
+ * never reaches 0 or 1.  The oracle takes it, on request, for the angle, the
+ * Box-Muller phase and the azimuth (not for the acceptance, which both forms
+ * draw at 32 bits), so that it samples the same angles as that form. */
+static double unif23(uint32_t a) { return ((double)(a >> 9) + 0.5) * 0x1p-23; }
+
 /* ------------------------------------------------------------------------ */
 /* Random permutation of a species list ("random binary pairs", Fig. 1 and   */
 /* Alg. 1): local indices ordered by (Philox word, index).                   */
@@ -326,6 +333,7 @@ typedef struct {
   double fE;
   int32_t pairing; /* ORC_ORDER_N, ORC_NXN or ORC_DUPLICITY */
   const double *sigma; /* [n_coll] cross-sections (ORC_HARD_SPHERE only) */
+  int32_t unif23;      /* 1: 23-bit uniforms for the angle and azimuth */
 } cfg_t;
 
 typedef struct {
@@ -391,9 +399,12 @@ static void scatter_pair_nr(const cfg_t *g, uint32_t cell, int coll,
                (4.0 * PI * g->eps0 * g->eps0 * mu * mu * um * um * um);
     if (!(s > 0.0)) return;
     draw4(g->seed, pair_k, cell, g->step, coll, PURPOSE_PAIR, r);
-    oc = oracle_sample_angle(g->method, s, unif(r[0]), unif(r[1]), &st);
+    if (g->unif23)
+      oc = oracle_sample_angle(g->method, s, unif23(r[0]), unif23(r[1]), &st);
+    else
+      oc = oracle_sample_angle(g->method, s, unif(r[0]), unif(r[1]), &st);
   }
-  double phi = 2.0 * PI * unif(r[2]);
+  double phi = 2.0 * PI * (g->unif23 && g->method != ORC_HARD_SPHERE ? unif23(r[2]) : unif(r[2]));
   double du[3];
   oracle_rotate(u, st, oc, phi, du);
   int ai, aj;
@@ -977,6 +988,13 @@ static int check_common(int64_t n, int32_t n_cells, int32_t n_species,
   return ORC_OK;
 }
 
+/* Threads of the cell loop (OpenMP, dynamic schedule).  Cells are
+ * independent and every random number is keyed by the cell, so the result
+ * does not depend on the thread count: every thread runs the same
+ * sequential code on its cells. */
+static int g_threads = 1;
+void oracle_set_threads(int32_t n) { g_threads = n > 0 ? n : 1; }
+
 /*
  * One collision step over particles grouped by (cell, species).
  * offsets[n_cells*n_species + 1]: particles of cell c, species s occupy
@@ -994,7 +1012,7 @@ int oracle_collide_sorted(
     int32_t sort_by_weight, int32_t max_passes, int32_t keep_on_fail, double f_E,
     double eps0, double c, const int32_t *cell_list, int32_t n_list,
     int64_t *counters, double *diag, int32_t *cell_corr_pairs,
-    const double *cross_section) {
+    const double *cross_section, int32_t uniform23) {
   int rc = check_common(n, n_cells, n_species, mass, charge, n_coll, coll_a,
                         coll_b, w, dt, coulomb_log, method, relativistic,
                         max_passes, f_E, eps0, c, cell_volume, cell_volume_scalar);
@@ -1013,26 +1031,50 @@ int oracle_collide_sorted(
   cfg_t g = {n_species, mass, charge, n_coll, coll_a, coll_b, dt, coulomb_log,
              eps0, c, seed, step, method, relativistic, moment_correction,
              sort_by_weight, max_passes, keep_on_fail, f_E, pairing,
-             cross_section};
+             cross_section, uniform23 ? 1 : 0};
   stats_t st;
   memset(&st, 0, sizeof(st));
   int32_t nl = cell_list ? n_list : n_cells;
-  for (int32_t li = 0; li < nl; ++li) {
-    int32_t cell = cell_list ? cell_list[li] : li;
-    if (cell < 0 || cell >= n_cells) return ORC_ERR_INVALID;
-    double dV = cell_volume ? cell_volume[cell] : cell_volume_scalar;
-    int32_t *cc = cell_corr_pairs ? &cell_corr_pairs[cell] : NULL;
-    if (cc) *cc = 0;
-    for (int k = 0; k < n_coll; ++k) {
-      int sa = coll_a[k], sb = coll_b[k];
-      int64_t oa = offsets[cell * S + sa], ob = offsets[cell * S + sb];
-      int32_t na = (int32_t)(offsets[cell * S + sa + 1] - oa);
-      int32_t nb = (int32_t)(offsets[cell * S + sb + 1] - ob);
-      rc = collide_one(&g, (uint32_t)cell, k, oa, na, ob, nb, sa, sb, dV, w, vx,
-                       vy, vz, &st, cc);
-      if (rc) return rc;
+  for (int32_t li = 0; cell_list && li < nl; ++li)
+    if (cell_list[li] < 0 || cell_list[li] >= n_cells) return ORC_ERR_INVALID;
+  int rc_all = ORC_OK;
+  /* the trace hook records into shared arrays: one thread then */
+  const int nthr = g_trace ? 1 : g_threads;
+#pragma omp parallel num_threads(nthr)
+  {
+    stats_t lst;
+    memset(&lst, 0, sizeof(lst));
+#pragma omp for schedule(dynamic, 1)
+    for (int32_t li = 0; li < nl; ++li) {
+      int32_t cell = cell_list ? cell_list[li] : li;
+      double dV = cell_volume ? cell_volume[cell] : cell_volume_scalar;
+      int32_t *cc = cell_corr_pairs ? &cell_corr_pairs[cell] : NULL;
+      if (cc) *cc = 0;
+      for (int k = 0; k < n_coll; ++k) {
+        int sa = coll_a[k], sb = coll_b[k];
+        int64_t oa = offsets[cell * S + sa], ob = offsets[cell * S + sb];
+        int32_t na = (int32_t)(offsets[cell * S + sa + 1] - oa);
+        int32_t nb = (int32_t)(offsets[cell * S + sb + 1] - ob);
+        int rc1 = collide_one(&g, (uint32_t)cell, k, oa, na, ob, nb, sa, sb, dV, w, vx,
+                              vy, vz, &lst, cc);
+        if (rc1) {
+#pragma omp critical(oracle_rc)
+          if (rc_all == ORC_OK) rc_all = rc1;
+          break;
+        }
+      }
+    }
+#pragma omp critical(oracle_stats)
+    {
+      st.pairs += lst.pairs;
+      st.corr_pairs += lst.corr_pairs;
+      st.failed += lst.failed;
+      st.collisions += lst.collisions;
+      if (lst.max_rel_dP > st.max_rel_dP) st.max_rel_dP = lst.max_rel_dP;
+      if (lst.max_rel_dE > st.max_rel_dE) st.max_rel_dE = lst.max_rel_dE;
     }
   }
+  if (rc_all) return rc_all;
   if (counters) {
     counters[0] = st.pairs;
     counters[1] = st.corr_pairs;
@@ -1063,7 +1105,7 @@ int oracle_collide(int64_t n, const int32_t *cells, const int32_t *species,
                    int32_t sort_by_weight, int32_t max_passes,
                    int32_t keep_on_fail, double f_E, double eps0, double c,
                    int64_t *counters, double *diag, int32_t *cell_corr_pairs,
-                   const double *cross_section) {
+                   const double *cross_section, int32_t uniform23) {
   if (n < 0 || n_cells < 0 || n_species < 1) return ORC_ERR_INVALID;
   const int64_t S = n_species, nk = (int64_t)n_cells * S;
   for (int64_t i = 0; i < n; ++i)
@@ -1093,7 +1135,7 @@ int oracle_collide(int64_t n, const int32_t *cells, const int32_t *species,
       gy, gz, cell_volume, cell_volume_scalar, dt, coulomb_log, seed, step,
       method, pairing, relativistic, moment_correction, sort_by_weight,
       max_passes, keep_on_fail, f_E, eps0, c, NULL, 0, counters, diag,
-      cell_corr_pairs, cross_section);
+      cell_corr_pairs, cross_section, uniform23);
   if (rc == ORC_OK) {
     for (int64_t j = 0; j < n; ++j) {
       vx[perm[j]] = gx[j];
@@ -1174,7 +1216,7 @@ int oracle_collide_sorted_traced(
       n, n_cells, n_species, offsets, mass, charge, n_coll, coll_a, coll_b, w,
       vx, vy, vz, NULL, cell_volume_scalar, dt, coulomb_log, seed, step, method,
       ORC_ORDER_N, relativistic, 1, sort_by_weight, 1, 0, f_E, 1.0, c, NULL, 0,
-      NULL, NULL, NULL, NULL);
+      NULL, NULL, NULL, NULL, 0);
   g_trace = NULL;
   return rc;
 }

@@ -96,6 +96,18 @@ struct DevBuf {
   }
 };
 
+// global scratch of the large-cell (GLOBAL layout) variants.  A context
+// owns one for its direct calls and every plan owns its own: a plan's graph
+// holds the scratch address, so a buffer the context later grows (and
+// reallocates) must never be the one a plan replays against.
+struct BigScratch {
+  DevBuf big4k, big32k;
+  void release() {
+    big4k.release();
+    big32k.release();
+  }
+};
+
 const void *const *kernel_table(int mode) {
   switch (mode) {
     case MODE_FP64: return mcc_kernel_table_fp64();
@@ -122,7 +134,8 @@ struct mcc_ctx {
   int n_cu = 0;
   bool validate = false;
   int32_t *err = nullptr;  // device error word
-  DevBuf lists, counts, big4k, big32k;
+  DevBuf lists, counts;
+  BigScratch big;  // large-cell scratch of the direct (non-plan) calls
   DevBuf n97;  // N97 A(s) table (built once)
   // per size bucket: the collide kernels' cell-claim and finished-workgroup
   // counters (zero between launches: each launch resets them at its end, so
@@ -145,6 +158,7 @@ struct mcc_plan {
   int variant[NBUCKET] = {};
   uint32_t hcount[NBUCKET] = {};  // cells per bucket (fixed for the plan)
   DevBuf lists, counts, step;
+  BigScratch big;          // large-cell scratch of this plan's kernels (its graph holds it)
   DevBuf prep, prep_word;  // weight data of the bound population (PREP_READ)
   mcc_stats *stats = nullptr;
   int32_t *cell_corr = nullptr;
@@ -286,18 +300,18 @@ int grid_of(mcc_ctx *ctx, int mode, int v) {
   return ctx->grid[mode][v];
 }
 
-bool ensure_big(mcc_ctx *ctx, int mode, int v) {
+bool ensure_big(mcc_ctx *ctx, BigScratch &B, int mode, int v) {
   const Variant V = variant_of(mode, v);
   if (V.layout != 2) return true;
   const uint64_t stride = big_stride_bytes(V.cap, mode == MODE_TAN);
-  if (V.cap > 4096) return ctx->big32k.ensure(stride * (uint64_t)ctx->n_cu);
-  return ctx->big4k.ensure(stride * (uint64_t)ctx->n_cu);
+  if (V.cap > 4096) return B.big32k.ensure(stride * (uint64_t)ctx->n_cu);
+  return B.big4k.ensure(stride * (uint64_t)ctx->n_cu);
 }
 
-void set_big_args(mcc_ctx *ctx, CollideArgs &A, int mode, int v) {
+void set_big_args(const BigScratch &B, CollideArgs &A, int mode, int v) {
   const Variant V = variant_of(mode, v);
   if (V.layout != 2) return;
-  A.big_scratch = V.cap > 4096 ? ctx->big32k.as<char>() : ctx->big4k.as<char>();
+  A.big_scratch = V.cap > 4096 ? B.big32k.as<char>() : B.big4k.as<char>();
   A.big_stride = big_stride_bytes(V.cap, mode == MODE_TAN);
 }
 
@@ -307,11 +321,11 @@ unsigned long long *g_phase = nullptr;
 #endif
 
 // enqueue the collide kernel of one bucket, reading its device work list
-mcc_status launch_bucket(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_t n_cells,
-                         const int32_t *lists, const uint32_t *counts, int b, int v,
-                         hipStream_t stream) {
+mcc_status launch_bucket(mcc_ctx *ctx, BigScratch &big, const CollideArgs &base, int mode,
+                         int32_t n_cells, const int32_t *lists, const uint32_t *counts, int b,
+                         int v, hipStream_t stream) {
   const void *const *tab = kernel_table(mode);
-  if (!ensure_big(ctx, mode, v)) return MCC_ERR_OOM;
+  if (!ensure_big(ctx, big, mode, v)) return MCC_ERR_OOM;
   CollideArgs A = base;
 #ifdef MCC_PHASE_TIMING
   A.phase = g_phase ? g_phase + 16 * b : nullptr;
@@ -319,7 +333,7 @@ mcc_status launch_bucket(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_
   A.cell_list = lists + (int64_t)b * std::max(n_cells, 1);
   A.cell_count = counts + b;
   A.work = ctx->work.as<uint32_t>() + WORK_QUEUES * WORK_STRIDE * b;
-  set_big_args(ctx, A, mode, v);
+  set_big_args(big, A, mode, v);
   void *kargs[] = {&A};
   HIP_TRY(hipLaunchKernel(tab[v], dim3(grid_of(ctx, mode, v)), dim3(variant_of(mode, v).tpc),
                           kargs, 0, stream));
@@ -329,13 +343,15 @@ mcc_status launch_bucket(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_
 // enqueue the collide kernels of all buckets, largest cells first
 // (host_counts: the buckets' cell counts when known on the host; empty
 // buckets are then not launched)
-mcc_status launch_buckets(mcc_ctx *ctx, const CollideArgs &base, int mode, int32_t n_cells,
-                          const int32_t *lists, const uint32_t *counts, const int *variant,
-                          hipStream_t stream, const uint32_t *host_counts = nullptr) {
+mcc_status launch_buckets(mcc_ctx *ctx, BigScratch &big, const CollideArgs &base, int mode,
+                          int32_t n_cells, const int32_t *lists, const uint32_t *counts,
+                          const int *variant, hipStream_t stream,
+                          const uint32_t *host_counts = nullptr) {
   for (int b = NBUCKET - 1; b >= 0; --b) {
     if (host_counts && host_counts[b] == 0) continue;
     const int v = variant[b] >= 0 ? variant[b] : default_variant(mode, b);
-    const mcc_status st = launch_bucket(ctx, base, mode, n_cells, lists, counts, b, v, stream);
+    const mcc_status st =
+        launch_bucket(ctx, big, base, mode, n_cells, lists, counts, b, v, stream);
     if (st != MCC_OK) return st;
   }
   return MCC_OK;
@@ -458,7 +474,8 @@ void mcc_destroy(mcc_ctx *ctx) {
   if (!ctx) return;
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
-  for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->big4k, &ctx->big32k, &ctx->ucnt, &ctx->tiles,
+  ctx->big.release();
+  for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->ucnt, &ctx->tiles,
                     &ctx->off, &ctx->cursor, &ctx->perm, &ctx->biglist, &ctx->bigcount,
                     &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97,
                     &ctx->work, &ctx->rb_gold, &ctx->rb_gnew, &ctx->rb_alist, &ctx->rb_flag,
@@ -527,7 +544,7 @@ mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t 
   HIP_TRY(launch_check_weights(n, weights, ctx->err, s));
   HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, ctx->lists.as<int32_t>(),
                               ctx->counts.as<uint32_t>(), cell_corr_pairs, ctx->err, s));
-  st = launch_buckets(ctx, A, mode_of(p, A), n_cells, ctx->lists.as<int32_t>(),
+  st = launch_buckets(ctx, ctx->big, A, mode_of(p, A), n_cells, ctx->lists.as<int32_t>(),
                       ctx->counts.as<uint32_t>(), ctx->variant, s);
   if (st != MCC_OK) return st;
   return finish(ctx);
@@ -572,7 +589,7 @@ mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells, int3
   if (n_cells == 0) return finish(ctx);
   HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, ctx->lists.as<int32_t>(),
                               ctx->counts.as<uint32_t>(), nullptr, ctx->err, s));
-  st = launch_buckets(ctx, A, MODE_TAN, n_cells, ctx->lists.as<int32_t>(),
+  st = launch_buckets(ctx, ctx->big, A, MODE_TAN, n_cells, ctx->lists.as<int32_t>(),
                       ctx->counts.as<uint32_t>(), ctx->variant, s);
   if (st != MCC_OK) return st;
   return finish(ctx);
@@ -737,7 +754,7 @@ mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int3
 static mcc_status plan_enqueue_step(mcc_plan *pl, hipStream_t s) {
   // counters are reset by kernels (no memset nodes in the graph)
   if (pl->stats) HIP_TRY(launch_zero_stats(pl->stats, s));
-  mcc_status st = launch_buckets(pl->ctx, pl->args, pl->mode, pl->n_cells,
+  mcc_status st = launch_buckets(pl->ctx, pl->big, pl->args, pl->mode, pl->n_cells,
                                  pl->lists.as<int32_t>(), pl->counts.as<uint32_t>(), pl->variant,
                                  s, pl->hcount);
   if (st != MCC_OK) return st;
@@ -816,12 +833,12 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
       double best = 1e300;
       for (int ci = 0; ci < 5 && kCandidates[b][ci] >= 0; ++ci) {
         const int v = kCandidates[b][ci];
-        if (!ensure_big(ctx, pl->mode, v)) continue;
+        if (!ensure_big(ctx, pl->big, pl->mode, v)) continue;
         CollideArgs A = T;
         A.cell_list = pl->lists.as<int32_t>() + (int64_t)b * std::max(n_cells, 1);
         A.cell_count = pl->counts.as<uint32_t>() + b;
         A.work = ctx->work.as<uint32_t>() + WORK_QUEUES * WORK_STRIDE * b;
-        set_big_args(ctx, A, pl->mode, v);
+        set_big_args(pl->big, A, pl->mode, v);
         void *kargs[] = {&A};
         float ms_best = 1e30f;
         for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
@@ -856,7 +873,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
   // workspace of every chosen variant exists before capture (no allocation
   // while capturing)
   for (int b = 0; b < NBUCKET; ++b)
-    if (!ensure_big(ctx, pl->mode, pl->variant[b])) {
+    if (!ensure_big(ctx, pl->big, pl->mode, pl->variant[b])) {
       mcc_plan_destroy(pl);
       return MCC_ERR_OOM;
     }
@@ -885,7 +902,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
     W.prep_word = pl->prep_word.as<uint16_t>();
     W.stats = nullptr;
     W.cell_corr = nullptr;
-    st = launch_buckets(ctx, W, pl->mode, n_cells, pl->lists.as<int32_t>(),
+    st = launch_buckets(ctx, pl->big, W, pl->mode, n_cells, pl->lists.as<int32_t>(),
                         pl->counts.as<uint32_t>(), pl->variant, s, pl->hcount);
     if (st == MCC_OK) st = from_hip(hipStreamSynchronize(s));
     if (st != MCC_OK) {
@@ -930,7 +947,7 @@ mcc_status mcc_plan_run_bucket(mcc_plan *pl, int32_t bucket, uint64_t step) {
   CollideArgs A = pl->args;
   A.step_dev = nullptr;
   A.step = step;
-  const mcc_status st = launch_bucket(pl->ctx, A, pl->mode, pl->n_cells, pl->lists.as<int32_t>(),
+  const mcc_status st = launch_bucket(pl->ctx, pl->big, A, pl->mode, pl->n_cells, pl->lists.as<int32_t>(),
                                       pl->counts.as<uint32_t>(), bucket, pl->variant[bucket],
                                       pl->ctx->stream);
   if (st != MCC_OK) return st;
@@ -979,6 +996,7 @@ void mcc_plan_destroy(mcc_plan *pl) {
   pl->step.release();
   pl->prep.release();
   pl->prep_word.release();
+  pl->big.release();
   delete pl;
 }
 

@@ -8,8 +8,10 @@
 //   REL  relativistic (Appendix A; FP64 only)
 //   LAY  where the cell lives: LAYOUT_LDS (everything in LDS), LAYOUT_COMPACT
 //        (LDS with aliased scratch and the weights read from the input, for
-//        cells up to 4096), LAYOUT_GLOBAL (per-workgroup global scratch; the
-//        workgroup is one wave so every exchange stays in program order)
+//        cells up to 4096), LAYOUT_GLOBAL (per-workgroup global scratch for
+//        cells up to MCC_MAX_CELL; one, four or eight waves per cell, whose
+//        scratch accesses the workgroup barriers order as they do LDS ones,
+//        the waves of a workgroup sharing their CU's L1)
 //
 // Data flow per cell: the cell's velocities and weights are staged in LDS
 // (coalesced loads), every collision of the list is applied in order, and

@@ -110,6 +110,46 @@ def oracle_sensitivity(wl, v0, vr, rerun, trials=3, rel=2.0 ** -50):
     return sens
 
 
+def count_sensitive_cells(wl, rerun_counts, trials=3, rel=2.0 ** -50):
+    """Cells whose energy-correction pair count the oracle itself changes
+    under independent few-ulp noise on its input velocities (rel = 2^-50).
+    The count is decided by where the running sum of f_E K over the ordered
+    pairs crosses |Delta E_s| (Eq. (23)); when that crossing lies within
+    rounding of a pair boundary, or when Delta E_s is rounding noise (equal
+    weights: no violation but rounding), the count is a rounding decision,
+    and the two implementations, which sum in different orders, may take it
+    differently.  `rerun_counts(p)` returns the oracle's per-cell counts for
+    a perturbed copy p of the workload."""
+    rng = np.random.default_rng(54321)
+    base = rerun_counts(wl.copy())
+    sens = set()
+    for _ in range(trials):
+        p = wl.copy()
+        for a in (p.vx, p.vy, p.vz):
+            a *= 1.0 + rel * rng.standard_normal(a.size)
+        sens |= set(np.nonzero(rerun_counts(p) != base)[0].tolist())
+    return sens
+
+
+def check_counts(wl, cg, cr, rerun_counts):
+    """Per-cell correction-pair counts equal the oracle's exactly, except in
+    cells where the oracle's own count is a rounding decision (see
+    count_sensitive_cells), where they may differ by one pair per collision.
+    Returns the number of such cells."""
+    diff = np.nonzero(np.asarray(cg) != np.asarray(cr))[0]
+    if diff.size == 0:
+        return 0
+    sens = count_sensitive_cells(wl, rerun_counts)
+    off = [int(c) for c in diff if int(c) not in sens]
+    assert not off, ("correction-pair counts differ in cells the oracle decides robustly",
+                     off[:10], [(int(cg[c]), int(cr[c])) for c in off[:10]])
+    ncoll = max(len(wl.collisions), 1)
+    assert np.all(np.abs(np.asarray(cg)[diff].astype(np.int64) - np.asarray(cr)[diff]) <= ncoll)
+    print("  correction-pair counts: %d cells differ, all rounding-decided" % diff.size,
+          flush=True)
+    return int(diff.size)
+
+
 # a particle may differ by up to this multiple of the oracle's own few-ulp
 # sensitivity (the two sides differ by a few ulp at every operation of a
 # chain of operations, not only at its input)

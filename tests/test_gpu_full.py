@@ -117,10 +117,10 @@ def test_full_workload_sampled_cells_and_conservation(ctx, full, mode):
     cells = _sample_cells(wl)
     sub, idx = _subset(wl, cells)
     ref = sub.copy()
-    oracle_step(ref, FIRST_STEP)
+    oracle_step(ref, FIRST_STEP, uniform23=(mode == "fp32"))
 
     def rerun(p):
-        oracle_step(p, FIRST_STEP)
+        oracle_step(p, FIRST_STEP, uniform23=(mode == "fp32"))
         return p.velocities()
 
     info = check_parity(sub, vg[:, idx], ref.velocities(), sub.velocities(),

@@ -20,9 +20,15 @@ parity is taken in two ways:
   conditioned (a step 10^4 times smaller; every layout and schedule path
   still runs), at 1e-12 sqrt(n): the rounding of n sequential pairs adds
   like a random walk;
-- at the real step, each particle within that bar or within 16 times the
-  oracle's measured response to 4-ulp input noise (the allowance of the
-  order-N tests, here without their 1e-6 cap).
+- at the real step, on cells up to 255 + 1 and 1 + 300 particles, each
+  particle within that bar or within 16 times the oracle's measured
+  response to 4-ulp input noise, capped at 1e-6 of the cell scale (the
+  order-N tests' allowance);
+- the 300 x 700 and 1024 x 1000 cells at the real step, where the oracle's
+  own response to 4-ulp input noise reaches 1e-5 and 1e-1, by what does not
+  depend on rounding: per-cell momentum and energy conserved to FP64
+  rounding, and each species' temperature change within its sampling
+  spread of the oracle's.
 FP32 kinematics: each pair's increment is good to ~3e-6 of |u|; the bar is
 1e-4 sqrt(n) on the well-conditioned inputs.
 """
@@ -31,6 +37,7 @@ import math
 import numpy as np
 import pytest
 
+import oracle
 from paper_2407_19151_amd import workloads as W
 
 from gpu_helpers import FP64_TOL, check_parity, custom_workload, oracle_step
@@ -42,6 +49,7 @@ NXN = 1
 SIZES = [(1, 0), (0, 1), (1, 1), (2, 1), (3, 5), (7, 2), (16, 16), (33, 64), (100, 27),
          (128, 129), (255, 1), (1, 300), (300, 700), (1024, 1000)]
 BIG = [(2100, 1900), (2500, 2000)]
+ILL = [(300, 700), (1024, 1000)]  # ill-conditioned at the real step
 DT_SMALL = 1e-4 * 0.05 * W.tau_e(2.0)
 
 
@@ -66,7 +74,7 @@ def _nxn_parity(ctx, wl, step, tol, conditioned=False, **over):
         return p.velocities()
 
     info = check_parity(wl, vg, ref.velocities(), v0, tol=tol,
-                        cond_tol=np.inf if conditioned else tol,
+                        cond_tol=1e-6 if conditioned else tol,
                         rerun=rerun if conditioned else None)
     print("  parity (tol %.1e): %s" % (tol, info), flush=True)
     assert sg["pairs"] == so["pairs"] and sg["collisions"] == so["collisions"]
@@ -97,8 +105,88 @@ def test_nxn_parity_large_cells_strict(ctx):
 
 
 def test_nxn_parity_real_step_conditioned(ctx):
-    wl = custom_workload(SIZES, seed=31)
-    _nxn_parity(ctx, wl, 2, _tol(SIZES), conditioned=True)
+    sizes = [s for s in SIZES if s not in ILL]
+    wl = custom_workload(sizes, seed=31)
+    _nxn_parity(ctx, wl, 2, _tol(sizes), conditioned=True)
+
+
+def _species_temps(wl, v):
+    m = wl.mass[wl.species]
+    return np.array([(m[k] * wl.w[k] * (v[:, k] ** 2).sum(0)).sum() / (3 * wl.w[k].sum())
+                     for k in (wl.species == 0, wl.species == 1)])
+
+
+@pytest.mark.parametrize("cell", ILL)
+def test_nxn_ill_conditioned_cell_conserves_and_relaxes_like_the_oracle(ctx, cell):
+    """The 300 x 700 and 1024 x 1000 electron-ion cells (ions 10-100 times
+    the electron weight) at the real step: 0.5e6 and 2.1e6 pairs in chains
+    of 700-2000, where rounding is amplified to 1e-5 and 1e-1 of the cell
+    scale on either side, so element-wise parity is not defined (one step
+    decorrelates the two realizations).  What is defined:
+    - the GPU conserves every cell's momentum and energy to FP64 rounding
+      (the moment correction, Eqs. (17)-(23)), and its pair and collision
+      counts are the oracle's;
+    - the temperature change of each species is a random variable with the
+      same law on both sides.  64 copies of the cell (same initial state;
+      their cell ids give them independent random numbers) give the GPU's
+      mean and spread over 8 steps; the oracle runs the first 16 (300 x 700)
+      or 8 (1024 x 1000) copies, and the two means agree within 4 standard
+      errors of their difference."""
+    import math
+    one = custom_workload([cell], seed=31)
+    K = 64
+    n1 = one.n
+    off = np.concatenate([[0], np.cumsum(np.tile(np.diff(one.offsets), K))]).astype(np.int64)
+    wl = W.Workload(name="ill", n_cells=K, n_species=2, offsets=off,
+                    cells=np.repeat(np.arange(K, dtype=np.int32), n1),
+                    species=np.tile(one.species, K), w=np.tile(one.w, K),
+                    vx=np.tile(one.vx, K), vy=np.tile(one.vy, K), vz=np.tile(one.vz, K),
+                    mass=one.mass, charge=one.charge, collisions=one.collisions, dt=one.dt,
+                    coulomb_log=one.coulomb_log, method=one.method, seed=one.seed)
+    m = wl.mass[wl.species] * wl.w
+
+    def temps(v):  # per copy: (T_e, T_i)
+        e2 = m * (v * v).sum(0)
+        out = np.zeros((K, 2))
+        for sp in (0, 1):
+            k = wl.species == sp
+            out[:, sp] = (np.bincount(wl.cells[k], e2[k], K)
+                          / (3 * np.bincount(wl.cells[k], wl.w[k], K)))
+        return out
+
+    T0 = temps(wl.velocities())
+    gw = wl.copy()
+    for step in range(2, 10):
+        vprev = gw.velocities()
+        vg, sg, _ = _gpu_step(ctx, gw, step, pairing=NXN)
+        for c in range(K):
+            sl = slice(c * n1, (c + 1) * n1)
+            mc = m[sl]
+            for d in range(3):
+                p0, p1 = math.fsum(mc * vprev[d, sl]), math.fsum(mc * vg[d, sl])
+                assert abs(p1 - p0) <= 1e-13 * math.fsum(mc * np.abs(vprev[d, sl])), (step, c, d)
+            e0 = math.fsum(mc * (vprev[:, sl] ** 2).sum(0))
+            e1 = math.fsum(mc * (vg[:, sl] ** 2).sum(0))
+            assert abs(e1 - e0) <= 1e-13 * e0, (step, c)
+        gw.vx[:], gw.vy[:], gw.vz[:] = vg
+    dg = temps(gw.velocities()) - T0
+    ko = 16 if cell[0] * cell[1] < 5e5 else 8
+    ref = wl.copy()
+    oracle.set_threads(16)
+    try:
+        for step in range(2, 10):
+            so = oracle_step(ref, step, pairing=NXN, cells=list(range(ko)))
+            assert so["pairs"] * K == sg["pairs"] * ko
+    finally:
+        oracle.set_threads(1)
+    do = (temps(ref.velocities()) - T0)[:ko]
+    mg, sgd = dg.mean(0), dg.std(0, ddof=1)
+    mo, sod = do.mean(0), do.std(0, ddof=1)
+    print("N x N %s, 8 steps: temperature change GPU %s +- %s (%d copies), oracle %s +- %s "
+          "(%d copies)" % (cell, mg, sgd, K, mo, sod, ko), flush=True)
+    se = np.sqrt(sgd ** 2 / K + sod ** 2 / ko)
+    assert np.all(np.abs(mo - mg) <= 4 * se)
+    assert np.all(np.abs(mg) > 4 * sgd / math.sqrt(K))  # a change well above the noise
 
 
 @pytest.mark.parametrize("wmode", ["equal", "lognormal", "two", "clustered"])
@@ -123,7 +211,7 @@ def test_nxn_parity_fp32_kinematics(ctx):
     v0 = wl.velocities().copy()
     vg, _, _ = _gpu_step(ctx, wl, 1, pairing=NXN, precision=native.MCC_FP32_KINEMATICS)
     ref = wl.copy()
-    oracle_step(ref, 1, pairing=NXN)
+    oracle_step(ref, 1, pairing=NXN, uniform23=True)
     tol = _tol(sizes, 1e-4)
     info = check_parity(wl, vg, ref.velocities(), v0, tol=tol, cond_tol=tol)
     print("fp32 N x N parity (tol %.1e): %s" % (tol, info), flush=True)
@@ -132,6 +220,15 @@ def test_nxn_parity_fp32_kinematics(ctx):
 def test_nxn_parity_relativistic(ctx):
     sizes = [(20, 16), (3, 1), (150, 150)]
     wl = custom_workload(sizes, seed=36, masses=(1.0, 1836.0), relativistic=True, c=1.0,
+                         dt=3e-6)
+    _nxn_parity(ctx, wl, 1, _tol(sizes))
+
+
+def test_nxn_parity_relativistic_one_wave_global_cell(ctx):
+    """A relativistic 1500 + 1200 cell (2049-4096 particles: the one-wave
+    global kernel of the N x N form), at the small step."""
+    sizes = [(1500, 1200)]
+    wl = custom_workload(sizes, seed=46, masses=(1.0, 1836.0), relativistic=True, c=1.0,
                          dt=3e-6)
     _nxn_parity(ctx, wl, 1, _tol(sizes))
 
@@ -243,25 +340,30 @@ def test_order_n_and_nxn_relaxation_differ_by_the_finite_s_factor(ctx):
 
 
 @pytest.mark.parametrize("pairing", [NXN, 2])
-def test_global_layout_waves_agree_fp32(ctx, pairing):
+def test_global_layout_fp32_matches_the_oracle(ctx, pairing):
     """N x N and duplicity pairing on a cell above 4096 particles with FP32
-    kinematics: the 8-wave global kernel against the one-wave one, element by
-    element (their FP64 forms match the oracle in the large-cell tests).  The
-    step is the well-conditioned small one, so only the order of the FP64
-    sums may differ."""
+    kinematics, in the one- and eight-wave global kernels, each against the
+    oracle with the FP32 form's 23-bit uniforms: N x N at the small step
+    and the bar 1e-4 sqrt(n) of the N x N FP32 test, duplicity at the
+    order-N FP32 bar."""
     from paper_2407_19151_amd import native
     sizes = [(2500, 2000), (30, 20)]
-    wl = custom_workload(sizes, seed=50 + pairing, dt=DT_SMALL)
+    dt = DT_SMALL if pairing == NXN else None
+    wl = custom_workload(sizes, seed=50 + pairing, dt=dt)
     v0 = wl.velocities().copy()
-    out = {}
+    ref = wl.copy()
+    so = oracle_step(ref, 1, pairing=pairing, uniform23=True)
+    tol = _tol(sizes, 1e-4) if pairing == NXN else 1e-4
     for variant in (10, 15):
+        print("pairing %d fp32, variant %d" % (pairing, variant), flush=True)
         try:
             ctx.set_variant(6, variant)
-            out[variant] = _gpu_step(ctx, wl, 1, pairing=pairing,
-                                     precision=native.MCC_FP32_KINEMATICS)
+            vg, sg, _ = _gpu_step(ctx, wl, 1, pairing=pairing,
+                                  precision=native.MCC_FP32_KINEMATICS)
         finally:
             ctx.set_variant(6, -1)
-    info = check_parity(wl, out[15][0], out[10][0], v0, tol=1e-5, cond_tol=1e-3)
-    print("pairing %d fp32, 8 waves against one: %s" % (pairing, info), flush=True)
-    for k in ("pairs", "collisions", "failed"):
-        assert out[15][1][k] == out[10][1][k]
+        info = check_parity(wl, vg, ref.velocities(), v0, tol=tol,
+                            cond_tol=tol if pairing == NXN else 0.2)
+        print("  against the oracle (tol %.1e): %s" % (tol, info), flush=True)
+        for k in ("pairs", "collisions", "failed"):
+            assert sg[k] == so[k]

@@ -15,7 +15,13 @@ reaches a few times the cell's RMS speed for tail particles: 1e-4 of the
 cell scale bounds it with margin.  Particles above that may only be members
 of an energy-correction pair whose cut-off moved (the same structural
 allowance as the FP64 tests: equal and opposite momentum change, parallel to
-the pair's relative velocity)."""
+the pair's relative velocity).
+
+The oracle reference of this form draws the angle, Box-Muller phase and
+azimuth uniforms from the top 23 bits of their words, as the form does
+(`uniform23`; the acceptance keeps its 32-bit uniform): without it, where
+N97's inverse CDF is steep (u -> 1 at large A) the 2^-23 grid alone moves
+an angle by more than the bar."""
 import numpy as np
 import pytest
 
@@ -61,7 +67,7 @@ def test_fp32_kinematics_step_parity_and_exact_conservation(ctx, method):
     st = native.read_stats(dw.stats)
     assert ctx.device_error() == 0
     ref = wl.copy()
-    so = oracle_step(ref, 3)
+    so = oracle_step(ref, 3, uniform23=True)
     info = check_parity(wl, vg, ref.velocities(), v0, tol=FP32_TOL, cond_tol=0.2)
     print("fp32 parity:", info, "stats:", st, flush=True)
     assert st["pairs"] == so["pairs"] and st["collisions"] == so["collisions"]
@@ -111,31 +117,30 @@ def test_fp32_relaxation_rate_matches_fp64_oracle(ctx):
     assert err32 < 1e-3
 
 
-def test_fp32_kinematics_global_layout_waves_agree(ctx):
-    """Cells above 4096 particles in global scratch with FP32 kinematics: the
-    4- and 8-wave variants against the one-wave variant, element by element.
-    Per pair they do the same arithmetic; only the order of the FP64 sums of
-    the momentum restore and the correction differs, so a difference beyond
-    rounding would be a fault of the multi-wave form.  (The FP64 forms of all
-    three match the oracle in the every-variant test.)"""
+def test_fp32_kinematics_large_cells_match_the_oracle(ctx):
+    """Cells above 4096 particles in global scratch with FP32 kinematics, in
+    the one-, four- and eight-wave variants, each against the oracle with
+    the form's 23-bit uniforms, element by element at the FP32 bar (the
+    correction's cut-off allowance as above)."""
     from paper_2407_19151_amd import native, runner
     from gpu_helpers import custom_workload
     sizes = [(2300, 2800), (4000, 3000), (100, 5000), (60, 40)]
     wl = custom_workload(sizes, seed=61)
     v0 = wl.velocities().copy()
-    out = {}
+    ref = wl.copy()
+    so = oracle_step(ref, 2, uniform23=True)
     for variant in (10, 14, 15):
+        print("fp32 large cells, variant %d" % variant, flush=True)
         dw = runner.DeviceWorkload(wl)
         try:
             ctx.set_variant(6, variant)
             runner.collide_sorted(ctx, dw, 2, params=runner.params_for(
                 wl, precision=native.MCC_FP32_KINEMATICS))
-            out[variant] = (dw.velocities(), native.read_stats(dw.stats))
+            vg, sg = dw.velocities(), native.read_stats(dw.stats)
         finally:
             ctx.set_variant(6, -1)
         assert ctx.device_error() == 0
-    for variant in (14, 15):
-        info = check_parity(wl, out[variant][0], out[10][0], v0, tol=1e-5, cond_tol=1e-3)
-        print("fp32, %d waves against one: %s" % (4 if variant == 14 else 8, info), flush=True)
+        info = check_parity(wl, vg, ref.velocities(), v0, tol=FP32_TOL, cond_tol=0.2)
+        print("  fp32 against the oracle: %s" % info, flush=True)
         for k in ("pairs", "collisions", "failed"):
-            assert out[variant][1][k] == out[10][1][k]
+            assert sg[k] == so[k]
