@@ -269,6 +269,42 @@ mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells,
                                   int32_t update_primal, mcc_stats *stats);
 
 /*
+ * Reverse-mode derivative of one step (the vector-Jacobian product): for the
+ * step of mcc_collide_sorted from the state (vx, vy, vz), device double[n]
+ * (read only; not stepped), and an adjoint g of its output velocities,
+ * (gx, gy, gz) device double[n] in/out, returns g J in place, J the Jacobian
+ * of the step with every random number and every discrete choice of the step
+ * fixed: the pairing, the acceptances, the correction order, the cut pair of
+ * Eq. (23) and the failure decision.  Through the cut pair, whose U is
+ * Delta E_s minus the f_E K of the pairs before it, the derivative reaches
+ * the energy violation of Eq. (18), its partition (Eq. (24)) and the
+ * momentum restore of Eq. (17).  The N97 parameter is differentiated as the
+ * root of Nanbu's equation (dA/ds = -exp(-s)/L'(A)); s is proportional to
+ * lnL (Eq. (12)).
+ *  g_coulomb_log  device double* or NULL: receives g dv'/dlnL (zero when
+ *                 lnL = 0, where no pair scatters)
+ * FP32 kinematics: the step is recomputed in that form, so the derivative
+ * is taken at its states and with its discrete choices and 23-bit uniforms;
+ * the pair Jacobians are evaluated in FP64.  A reset (Sec. 6.2) collision
+ * passes the adjoint through unchanged.
+ * Scratch: per workgroup, 228 B per particle of capacity (4096, or
+ * MCC_MAX_CELL for the cells above 4096): about 0.5 GB on 256 compute units
+ * for cells up to 4096, 1.9 GB more once a cell above 4096 occurs; owned by
+ * the context.  The call waits once on the context's stream (to read the
+ * cell counts per size bucket) before it enqueues the kernels.
+ * Errors: MCC_ERR_UNSUPPORTED for the relativistic form, a pairing other
+ * than ORDER_N, hard spheres or max_passes > 1.
+ */
+mcc_status mcc_collide_adjoint(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                               const int64_t *offsets, const double *weights, const double *vx,
+                               const double *vy, const double *vz, double *gx, double *gy,
+                               double *gz, const double *cell_volume,
+                               double cell_volume_scalar, const mcc_species *species,
+                               int32_t n_coll, const mcc_collision *coll, double dt,
+                               double coulomb_log, uint64_t seed, uint64_t step,
+                               const mcc_params *p, double *g_coulomb_log);
+
+/*
  * Cell binning alone (the grouping used by mcc_collide):
  *  offsets_out  device int64[n_cells*n_species + 1]
  *  perm_out     device int32[n]: perm_out[j] = original index of the j-th

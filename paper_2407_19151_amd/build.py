@@ -14,7 +14,8 @@ SOURCES = ["mcc_collide_fp64.hip", "mcc_collide_fp32.hip", "mcc_collide_rel.hip"
            "mcc_collide_tan.hip", "mcc_collide_fp64_diag.hip", "mcc_collide_fp32_diag.hip",
            "mcc_collide_rel_diag.hip", "mcc_collide_fp64_nxn.hip", "mcc_collide_fp32_nxn.hip",
            "mcc_collide_rel_nxn.hip", "mcc_collide_fp64_dup.hip", "mcc_collide_fp32_dup.hip",
-           "mcc_collide_rel_dup.hip", "mcc_aux.hip", "mcc_rebin.hip", "mcc_api.hip"]
+           "mcc_collide_rel_dup.hip", "mcc_aux.hip", "mcc_rebin.hip", "mcc_adjoint.hip",
+           "mcc_api.hip"]
 ARCH = os.environ.get("MCC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-fno-strict-aliasing", "--offload-arch=" + ARCH,
          # packed FP32 instructions are kept out of the generated code

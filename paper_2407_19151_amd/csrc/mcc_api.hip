@@ -62,7 +62,13 @@ hipError_t launch_gather(int64_t n, const int32_t *perm, const double *w, const 
 hipError_t launch_scatter_back(int64_t n, const int32_t *perm, const double *gx,
                                const double *gy, const double *gz, double *vx, double *vy,
                                double *vz, hipStream_t s);
+struct AdjointArgs;
+hipError_t launch_adjoint(const AdjointArgs &base, bool fp32, const int32_t *lists,
+                          const uint32_t *counts, int32_t n_cells, int b, int tpc, int cap,
+                          int grid, hipStream_t s);
+hipError_t launch_sum_f64(const double *x, int64_t n, double *out, hipStream_t s);
 }  // namespace mcc
+#include "mcc_adjoint_args.hpp"
 
 using namespace mcc;
 
@@ -143,6 +149,9 @@ struct mcc_ctx {
   DevBuf work;
   // unsorted entry
   DevBuf ucnt, tiles, off, cursor, perm, biglist, bigcount, canon, gw, gx, gy, gz;
+  // reverse-mode form: per-workgroup scratch (cells up to 4096 particles,
+  // and above), per-cell lnL adjoints
+  DevBuf adj_small, adj_big, adj_part;
   // incremental re-binning
   DevBuf rb_gold, rb_gnew, rb_alist, rb_flag, rb_mpre, rb_leave, rb_arrive, rb_acur, rb_cnt,
       rb_aoff, rb_rec;
@@ -480,7 +489,8 @@ void mcc_destroy(mcc_ctx *ctx) {
                     &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97,
                     &ctx->work, &ctx->rb_gold, &ctx->rb_gnew, &ctx->rb_alist, &ctx->rb_flag,
                     &ctx->rb_mpre, &ctx->rb_leave, &ctx->rb_arrive, &ctx->rb_acur,
-                    &ctx->rb_cnt, &ctx->rb_aoff, &ctx->rb_rec})
+                    &ctx->rb_cnt, &ctx->rb_aoff, &ctx->rb_rec, &ctx->adj_small, &ctx->adj_big,
+                    &ctx->adj_part})
     b->release();
   if (ctx->err) (void)hipFree(ctx->err);
   delete ctx;
@@ -592,6 +602,95 @@ mcc_status mcc_collide_sorted_jvp(mcc_ctx *ctx, int64_t n, int32_t n_cells, int3
   st = launch_buckets(ctx, ctx->big, A, MODE_TAN, n_cells, ctx->lists.as<int32_t>(),
                       ctx->counts.as<uint32_t>(), ctx->variant, s);
   if (st != MCC_OK) return st;
+  return finish(ctx);
+}
+
+mcc_status mcc_collide_adjoint(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_species,
+                               const int64_t *offsets, const double *weights, const double *vx,
+                               const double *vy, const double *vz, double *gx, double *gy,
+                               double *gz, const double *cell_volume,
+                               double cell_volume_scalar, const mcc_species *species,
+                               int32_t n_coll, const mcc_collision *coll, double dt,
+                               double coulomb_log, uint64_t seed, uint64_t step,
+                               const mcc_params *p, double *g_coulomb_log) {
+  if (!ctx || !offsets) return MCC_ERR_INVALID;
+  mcc_status st = check_step(n, n_cells, n_species, weights, vx, vy, vz, cell_volume,
+                             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, p);
+  if (st != MCC_OK) return st;
+  if (n > 0 && (!gx || !gy || !gz)) return MCC_ERR_INVALID;
+  if (p->relativistic || p->pairing != MCC_PAIRING_ORDER_N || p->method == MCC_HARD_SPHERE ||
+      p->max_passes != 1)
+    return MCC_ERR_UNSUPPORTED;
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (!ensure_lists(ctx, ctx->lists, ctx->counts, n_cells) ||
+      !ctx->adj_part.ensure(sizeof(double) * (size_t)std::max(n_cells, 1)))
+    return MCC_ERR_OOM;
+  CollideArgs F;
+  fill_args(F, n, n_cells, n_species, offsets, weights, const_cast<double *>(vx),
+            const_cast<double *>(vy), const_cast<double *>(vz), cell_volume, cell_volume_scalar,
+            species, n_coll, coll, dt, coulomb_log, seed, step, p, nullptr, nullptr, ctx->err,
+            ctx->n97.as<double2>());
+  AdjointArgs A;
+  std::memset(&A, 0, sizeof(A));
+  A.offsets = offsets;
+  A.w = weights;
+  A.vx = vx;
+  A.vy = vy;
+  A.vz = vz;
+  A.gx = gx;
+  A.gy = gy;
+  A.gz = gz;
+  A.cell_volume = cell_volume;
+  A.dV = cell_volume_scalar;
+  A.n = n;
+  A.n_cells = n_cells;
+  A.S = n_species;
+  A.n_coll = n_coll;
+  A.method = p->method;
+  A.corr = F.corr;
+  A.sortw = F.sortw;
+  A.keep = F.keep;
+  A.fE = F.fE;
+  A.inv_lnl = coulomb_log > 0.0 ? 1.0 / coulomb_log : 0.0;
+  A.seed = seed;
+  A.step = step;
+  for (int s = 0; s < n_species; ++s) A.mass[s] = F.mass[s];
+  for (int k = 0; k < n_coll; ++k) A.coll[k] = F.coll[k];
+  A.lnl_part = ctx->adj_part.as<double>();
+  A.err = ctx->err;
+  A.n97 = ctx->n97.as<double2>();
+  hipStream_t s = ctx->stream;
+  HIP_TRY(launch_check_weights(n, weights, ctx->err, s));
+  HIP_TRY(launch_fill_u32(ctx->counts.as<uint32_t>(), 0u, NBUCKET, s));
+  HIP_TRY(launch_fill_u32(reinterpret_cast<uint32_t *>(ctx->adj_part.p), 0u,
+                          2 * (int64_t)std::max(n_cells, 1), s));
+  if (n_cells > 0) {
+    HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, ctx->lists.as<int32_t>(),
+                                ctx->counts.as<uint32_t>(), nullptr, ctx->err, s));
+    // the cell counts per size bucket size the scratch (one wait on the stream)
+    uint32_t hc[NBUCKET];
+    HIP_TRY(hipMemcpyAsync(hc, ctx->counts.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int b = 0; b < NBUCKET; ++b) {
+      if (hc[b] == 0) continue;
+      // threads per cell of the forward-mode variant of the bucket, so the
+      // per-cell sums (and the choices they decide) round as there
+      const int v = ctx->variant[b] >= 0 ? ctx->variant[b] : default_variant(MODE_TAN, b);
+      const Variant V = variant_of(MODE_TAN, v);
+      const bool big = kBucketCap[b] > 4096;
+      const int tpc = big ? 64 : V.tpc;
+      const int cap = big ? MCC_MAX_CELL : 4096;
+      const int grid = (int)std::min<uint32_t>(hc[b], (uint32_t)(big ? ctx->n_cu : ctx->n_cu * 2));
+      DevBuf &buf = big ? ctx->adj_big : ctx->adj_small;
+      A.stride = adj_stride_bytes(cap);
+      if (!buf.ensure(A.stride * (uint64_t)grid)) return MCC_ERR_OOM;
+      A.scratch = buf.as<char>();
+      HIP_TRY(launch_adjoint(A, p->precision == MCC_FP32_KINEMATICS, ctx->lists.as<int32_t>(),
+                             ctx->counts.as<uint32_t>(), n_cells, b, tpc, cap, grid, s));
+    }
+  }
+  if (g_coulomb_log)
+    HIP_TRY(launch_sum_f64(ctx->adj_part.as<double>(), n_cells, g_coulomb_log, s));
   return finish(ctx);
 }
 

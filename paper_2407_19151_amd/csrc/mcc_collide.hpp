@@ -174,6 +174,57 @@ __device__ __forceinline__ double langevin_prime(double A) {
   return ra * ra - 4.0 * (em + 1.0) / (em * em);
 }
 
+// Tangent of a pair's velocity change du (the rotation of u = v_I - v_J by
+// the sampled angle, TA77 form) along (tu, ts): tu the tangent of u and ts
+// that of s, with the random numbers fixed; u0 the angle's uniform and A
+// Nanbu's parameter of s (N97).  oc = 1 - cos(theta), st = sin(theta), and
+// (sp, cp) the azimuth's sine and cosine, as the primal sampled them.
+__device__ __forceinline__ void rot_tangent(int method, double ux, double uy, double uz, double um,
+                                            double s, double oc, double st, double sp,
+                                            double cp, double u0, double A, double tux,
+                                            double tuy, double tuz, double ts, double &tdx,
+                                            double &tdy, double &tdz) {
+  using K = KMath<double>;
+  const double tum = (ux * tux + uy * tuy + uz * tuz) / um;
+  // tangent of 1 - cos(theta) and sin(theta)
+  double toc = 0.0;
+  if (method == 0) {  // TA77: delta = sqrt(s/2) z scales as sqrt(s)
+    if (oc < 2.0) {
+      const double d2 = oc / (2.0 - oc);  // delta^2, from oc = 2 d2 / (1 + d2)
+      // d oc / d(delta^2) = 2 / (1 + d2)^2 and d(delta^2) = delta^2 ds / s
+      toc = 2.0 / ((1.0 + d2) * (1.0 + d2)) * d2 * ts / s;
+    }
+  } else {
+    if (A > 0.0 && !__builtin_isinf(A) && oc > 0.0 && oc < 2.0) {
+      const double e = expm1(-2.0 * A);
+      const double den = 1.0 + u0 * e;
+      const double dl_dA = -2.0 * u0 * (e + 1.0) / den;  // d log1p(u0 e) / dA
+      const double doc_dA = -dl_dA / A - oc / A;
+      const double dA_ds = -exp(-s) / langevin_prime(A);
+      toc = doc_dA * dA_ds * ts;
+    }
+  }
+  // st^2 = oc (2 - oc) for either sign of st
+  const double tst = st != 0.0 ? (1.0 - oc) * toc / st : 0.0;
+  // tangent of the rotation
+  const double up2 = ux * ux + uy * uy;
+  const double up = K::sqrt_(up2);
+  if (up > 0.0) {
+    const double tup = (ux * tux + uy * tuy) / up;
+    const double ax = ux / up, ay = uy / up;
+    const double tax = (tux - ax * tup) / up, tay = (tuy - ay * tup) / up;
+    tdx = tax * uz * st * cp + ax * (tuz * st + uz * tst) * cp - tay * um * st * sp -
+          ay * (tum * st + um * tst) * sp - tux * oc - ux * toc;
+    tdy = tay * uz * st * cp + ay * (tuz * st + uz * tst) * cp + tax * um * st * sp +
+          ax * (tum * st + um * tst) * sp - tuy * oc - uy * toc;
+    tdz = -(tup * st + up * tst) * cp - tuz * oc - uz * toc;
+  } else {
+    tdx = (tum * st + um * tst) * cp;
+    tdy = (tum * st + um * tst) * sp;
+    tdz = -tuz * oc - uz * toc;
+  }
+}
+
 __device__ __attribute__((noinline)) void scatter_pair_nr_tan(
     double *vx, double *vy, double *vz, double *tx, double *ty, double *tz, const double *w,
     int I, int J, uint32_t kp, double coef_f_nmin_dV, double fa, double fb, int method,
@@ -208,45 +259,10 @@ __device__ __attribute__((noinline)) void scatter_pair_nr_tan(
   const double tux = tx[I] - tx[J], tuy = ty[I] - ty[J], tuz = tz[I] - tz[J];
   const double tum = (ux * tux + uy * tuy + uz * tuz) / um;
   const double ts = s * (dlnl - 3.0 * tum / um);
-  // tangent of 1 - cos(theta) and sin(theta)
-  double toc = 0.0;
-  if (method == 0) {  // TA77: delta = sqrt(s/2) z scales as sqrt(s)
-    if (oc < 2.0) {
-      const double d2 = oc / (2.0 - oc);  // delta^2, from oc = 2 d2 / (1 + d2)
-      // d oc / d(delta^2) = 2 / (1 + d2)^2 and d(delta^2) = delta^2 ds / s
-      toc = 2.0 / ((1.0 + d2) * (1.0 + d2)) * d2 * ts / s;
-    }
-  } else {
-    const double A = n97_A_fast<double>(s, n97tab);
-    if (A > 0.0 && !__builtin_isinf(A) && oc > 0.0 && oc < 2.0) {
-      const double e = expm1(-2.0 * A);
-      const double den = 1.0 + K::u(r.x) * e;
-      const double dl_dA = -2.0 * K::u(r.x) * (e + 1.0) / den;  // d log1p(u0 e) / dA
-      const double doc_dA = -dl_dA / A - oc / A;
-      const double dA_ds = -exp(-s) / langevin_prime(A);
-      toc = doc_dA * dA_ds * ts;
-    }
-  }
-  // st^2 = oc (2 - oc) for either sign of st
-  const double tst = st != 0.0 ? (1.0 - oc) * toc / st : 0.0;
-  // tangent of the rotation
+  const double A = method == 0 ? 0.0 : n97_A_fast<double>(s, n97tab);
   double tdx, tdy, tdz;
-  const double up2 = ux * ux + uy * uy;
-  const double up = K::sqrt_(up2);
-  if (up > 0.0) {
-    const double tup = (ux * tux + uy * tuy) / up;
-    const double ax = ux / up, ay = uy / up;
-    const double tax = (tux - ax * tup) / up, tay = (tuy - ay * tup) / up;
-    tdx = tax * uz * st * cp + ax * (tuz * st + uz * tst) * cp - tay * um * st * sp -
-          ay * (tum * st + um * tst) * sp - tux * oc - ux * toc;
-    tdy = tay * uz * st * cp + ay * (tuz * st + uz * tst) * cp + tax * um * st * sp +
-          ax * (tum * st + um * tst) * sp - tuy * oc - uy * toc;
-    tdz = -(tup * st + up * tst) * cp - tuz * oc - uz * toc;
-  } else {
-    tdx = (tum * st + um * tst) * cp;
-    tdy = (tum * st + um * tst) * sp;
-    tdz = -tuz * oc - uz * toc;
-  }
+  rot_tangent(method, ux, uy, uz, um, s, oc, st, sp, cp, K::u(r.x), A, tux, tuy, tuz, ts, tdx,
+              tdy, tdz);
   if (ai) {
     vx[I] = vix + fa * dx;
     vy[I] = viy + fa * dy;

@@ -34,7 +34,7 @@ EXPORTS = ["mcc_default_params", "mcc_status_string", "mcc_create", "mcc_set_str
            "mcc_bin", "mcc_rebin", "mcc_rebin_out", "mcc_plan_create", "mcc_plan_run",
            "mcc_plan_describe",
            "mcc_plan_destroy", "mcc_sample_angles", "mcc_plan_run_bucket",
-           "mcc_collide_sorted_jvp"]
+           "mcc_collide_sorted_jvp", "mcc_collide_adjoint"]
 
 
 class mcc_species(C.Structure):
@@ -107,6 +107,10 @@ def load(path: str = LIB_PATH):
                                          C.POINTER(mcc_species), i32, C.POINTER(mcc_collision),
                                          f64, f64, f64, u64, u64, C.POINTER(mcc_params), i32, P]
     L.mcc_collide_sorted_jvp.restype = C.c_int
+    L.mcc_collide_adjoint.argtypes = [P, i64, i32, i32, P, P, P, P, P, P, P, P, P, f64,
+                                      C.POINTER(mcc_species), i32, C.POINTER(mcc_collision),
+                                      f64, f64, u64, u64, C.POINTER(mcc_params), P]
+    L.mcc_collide_adjoint.restype = C.c_int
     L.mcc_bin.argtypes = [P, i64, P, P, i32, i32, P, P]
     L.mcc_rebin.argtypes = [P, i64, i32, i32, P, P, P, P, P, P, P, P]
     L.mcc_rebin.restype = C.c_int
@@ -304,6 +308,28 @@ class Context:
             float(coulomb_log), float(coulomb_log_tangent), int(seed), int(step), C.byref(p),
             int(bool(update_primal)), _ptr(stats))
         _check("mcc_collide_sorted_jvp", rc)
+
+    def collide_adjoint(self, offsets, weights, vx, vy, vz, gx, gy, gz, *, n_cells: int,
+                        mass, charge, collisions, dt: float, coulomb_log: float, seed: int,
+                        step: int, params: Optional[mcc_params] = None, cell_volume=1.0,
+                        g_coulomb_log=None):
+        """mcc_collide_adjoint: (gx, gy, gz) <- g J in place for the step from
+        (vx, vy, vz); g_coulomb_log (1-element float64 device tensor or None)
+        receives g dv'/dlnL."""
+        import torch
+        n, cv, cvs, sp, co, p = self._common(weights, vx, vy, vz, cell_volume, mass, charge,
+                                             collisions, params, None, None, n_cells)
+        _expect(offsets, torch.int64, n_cells * len(mass) + 1, "offsets")
+        for name, t in (("gx", gx), ("gy", gy), ("gz", gz)):
+            _expect(t, torch.float64, n, name)
+        if g_coulomb_log is not None:
+            _expect(g_coulomb_log, torch.float64, 1, "g_coulomb_log")
+        self._stream()
+        rc = self.L.mcc_collide_adjoint(
+            self.h, n, n_cells, len(mass), _ptr(offsets), _ptr(weights), _ptr(vx), _ptr(vy),
+            _ptr(vz), _ptr(gx), _ptr(gy), _ptr(gz), cv, cvs, sp, len(collisions), co, float(dt),
+            float(coulomb_log), int(seed), int(step), C.byref(p), _ptr(g_coulomb_log))
+        _check("mcc_collide_adjoint", rc)
 
     def collide(self, cells, species_id, weights, vx, vy, vz, *, n_cells: int, mass, charge,
                 collisions, dt: float, coulomb_log: float, seed: int, step: int,

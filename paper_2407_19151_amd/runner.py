@@ -70,6 +70,22 @@ def collide_sorted_jvp(ctx: native.Context, dw: DeviceWorkload, tangent, step: i
                            cell_volume=wl.cell_volume, update_primal=update_primal)
 
 
+def collide_adjoint(ctx: native.Context, dw: DeviceWorkload, v, g, step: int,
+                    g_lnl=None, params: Optional[native.mcc_params] = None,
+                    coulomb_log: Optional[float] = None):
+    """g <- g J for the step of dw's population from the state v ((3, n)
+    float64 device tensors; g in place); g_lnl (1-element device tensor or
+    None) receives g dv'/dlnL."""
+    wl = dw.wl
+    ctx.collide_adjoint(dw.offsets, dw.w, v[0], v[1], v[2], g[0], g[1], g[2],
+                        n_cells=wl.n_cells, mass=wl.mass, charge=wl.charge,
+                        collisions=wl.collisions, dt=wl.dt,
+                        coulomb_log=wl.coulomb_log if coulomb_log is None else coulomb_log,
+                        seed=wl.seed, step=step,
+                        params=params if params is not None else params_for(wl),
+                        cell_volume=wl.cell_volume, g_coulomb_log=g_lnl)
+
+
 def collide_unsorted(ctx: native.Context, dw: DeviceWorkload, step: int,
                      params: Optional[native.mcc_params] = None):
     wl = dw.wl

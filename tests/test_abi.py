@@ -59,12 +59,15 @@ def test_struct_layout_matches_header():
 int main(void) {
   F(mcc_params, method) F(mcc_params, precision) F(mcc_params, relativistic)
   F(mcc_params, moment_correction) F(mcc_params, sort_by_weight) F(mcc_params, max_passes)
-  F(mcc_params, on_failure) F(mcc_params, diagnostics) F(mcc_params, f_E)
-  F(mcc_params, eps0) F(mcc_params, c)
+  F(mcc_params, on_failure) F(mcc_params, diagnostics) F(mcc_params, pairing)
+  F(mcc_params, f_E) F(mcc_params, eps0) F(mcc_params, c)
   F(mcc_stats, pairs) F(mcc_stats, corr_pairs) F(mcc_stats, failed)
   F(mcc_stats, collisions) F(mcc_stats, max_rel_dP) F(mcc_stats, max_rel_dE)
   F(mcc_species, mass) F(mcc_species, charge) F(mcc_collision, a) F(mcc_collision, b)
+  F(mcc_collision, cross_section)
   printf("sizeof mcc_params %zu\nsizeof mcc_stats %zu\n", sizeof(mcc_params), sizeof(mcc_stats));
+  printf("sizeof mcc_species %zu\nsizeof mcc_collision %zu\n", sizeof(mcc_species),
+         sizeof(mcc_collision));
   return 0;
 }
 '''
