@@ -34,8 +34,20 @@ sys.path.insert(0, ROOT)
 # v read 24, v write 24, and 8 for the cell and species ids a particle
 # carries (here implied by the offsets, whose per-group entries are < 0.1 %)
 BYTES_PER_PARTICLE_STEP = 64
+# the unsorted entry: the sorted step plus binning (ids in, permutation out:
+# 12 B) and the payload moved each way (w, v gathered: 32 + 32 B; v
+# scattered back: 24 + 24 B) and the permutation read twice (8 B): 150 B
+BYTES_UNSORTED = 150
+BYTES_BIN = 12  # binning alone: cell and species ids read, permutation written
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_c3_hbm_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "collide_c3_valu.txt")
+RELAX_FILE = os.path.join(ROOT, "tests", "golden", "c3_4096_relaxation_oracle.txt")
+# MI355X: 256 CUs of 4 SIMDs at 2.4 GHz; a wave64 VALU instruction holds a
+# SIMD for 4 cycles (16 lanes), so 6.14e11 wave instructions/s; FP64 vector
+# peak 78.6 TFLOP/s
+VALU_PEAK_WINST = 256 * 4 * 2.4e9 / 4
+FP64_PEAK_TFLOPS = 78.6
 BUCKET_CAP = [128, 256, 512, 1024, 2048, 4096, 32768]
 
 
@@ -50,6 +62,9 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="time the candidate variants per bucket instead of the built-in table")
     ap.add_argument("--only", choices=["fp32", "fp64"], default=None)
+    ap.add_argument("--quick", action="store_true",
+                    help="only the plan timings (for profiling runs): no autotuned plan, "
+                         "per-call, unsorted, copy-ceiling or relaxation legs")
     ap.add_argument("--paper-test1", action="store_true",
                     help="only time the paper's Test 1 cases (SI units, 180 cells, FP64) and exit")
     ap.add_argument("--paper-test2", action="store_true",
@@ -125,6 +140,27 @@ def read_traffic():
     return {k: (fk * 1024 * ff + wk * 1024 * wf) for k, (fk, wk) in table.items()}
 
 
+def read_valu():
+    """Per-launch VALU wave instructions and FP64 operations of each collide
+    kernel from the committed rocprofv3 counter summary, if it was taken
+    from the current sources: {(mode, tpcxcap, L<layout>): (valu, fp64_flops)}."""
+    if not os.path.exists(VALU_FILE):
+        return None
+    table, src = {}, None
+    for line in open(VALU_FILE):
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "source_sha256":
+            src = f[1]
+        elif f[0] == "kernel":
+            # kernel <mode> <tpc>x<cap> L<layout> valu <V> fp64_flops <F> ...
+            table[(f[1], f[2], f[3])] = (float(f[5]), float(f[7]))
+    if src != kernel_source_hash():
+        return None
+    return table
+
+
 def events():
     import torch
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -168,23 +204,167 @@ def bucket_particles(wl):
     return {int(k): int(sizes[b == k].sum()) for k in np.unique(b)}
 
 
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count() or 1, model
+
+
 def cpu_baseline(seconds):
-    """The oracle, single-threaded, on a bounded sample of the same workload."""
+    """The oracle on a bounded sample of the same workload: one thread, then
+    every host core (its cell loop in OpenMP threads; the same result bit for
+    bit)."""
     import oracle
     from paper_2407_19151_amd import workloads as W
-    sub = W.config3(n_cells=2048, seed_data=3)
-    pc = sub.particle_collisions_per_step()
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        oracle.run_workload(sub, steps=1, first_step=steps)
-        steps += 1
-        if time.perf_counter() - t0 > seconds:
-            break
-    dt = time.perf_counter() - t0
-    return dict(value=pc * steps / dt, unit="particle-collisions/s", cores=1, kind="oracle",
-                sample="%d steps of the first 2048 cells of the same workload (%d particles, "
-                       "N97, FP64, correction on), one thread" % (steps, sub.n))
+    nproc, model = host_cpu()
+    out = {}
+    for threads in (1, nproc):
+        sub = W.config3(n_cells=2048, seed_data=3)
+        pc = sub.particle_collisions_per_step()
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            oracle.run_workload(sub, steps=1, first_step=steps)
+            steps += 1
+            if time.perf_counter() - t0 > seconds / 2:
+                break
+        dt = time.perf_counter() - t0
+        out[threads] = (pc * steps / dt, steps, sub.n)
+    oracle.set_threads(1)
+    v1, s1, n1 = out[1]
+    va, sa, _ = out[nproc]
+    return dict(value=va, unit="particle-collisions/s", cores=nproc, kind="oracle",
+                sample="%d steps (%d threads) and %d steps (1 thread) of the first 2048 cells "
+                       "of the same recipe (%d particles, N97, FP64, correction on)"
+                       % (sa, nproc, s1, n1),
+                one_thread=v1, nproc=nproc, cpu=model)
+
+
+def copy_ceiling():
+    """Device-to-device copy of 1 GiB (float64), the best of 5, in GB/s
+    (bytes read plus bytes written)."""
+    import torch
+    n = (1 << 30) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    best = 1e30
+    for _ in range(6):
+        e0, e1 = events()
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (best * 1e-3) / 1e9
+
+
+def relaxation_rate_error(ctx):
+    """The FP32-kinematics and FP64 steps against the oracle over 200 steps
+    of 4096 cells of the same recipe: the relaxation rate of T_e - T_i (slope
+    of its logarithm against the step) and the largest temperature
+    deviation.  The oracle's trajectory is the committed reference written
+    by tests/golden/make_c3_relaxation_reference.py."""
+    import torch
+    from paper_2407_19151_amd import autodiff, native, runner
+    from paper_2407_19151_amd import workloads as W
+    ref = np.loadtxt(RELAX_FILE)
+    steps = int(ref[-1, 0])
+    wl = W.config3(n_cells=4096)
+    out = {}
+
+    def rate(T):
+        return -np.polyfit(np.arange(T.shape[0]), np.log(T[:, 0] - T[:, 1]), 1)[0]
+
+    r_or = rate(ref[:, 1:3])
+    for mode, prec in (("fp32", native.MCC_FP32_KINEMATICS), ("fp64", native.MCC_FP64)):
+        dw = runner.DeviceWorkload(wl)
+        plan = runner.make_plan(ctx, dw, params=runner.params_for(wl, precision=prec),
+                                autotune=False)
+        v = torch.stack([dw.vx, dw.vy, dw.vz])
+        T = [autodiff.species_temperatures(wl, v)]
+        for k in range(steps):
+            plan.run(k, 1)
+            T.append(autodiff.species_temperatures(wl, torch.stack([dw.vx, dw.vy, dw.vz])))
+        plan.close()
+        T = torch.stack(T).cpu().numpy()
+        out[mode] = dict(rate_rel_err=abs(rate(T) / r_or - 1.0),
+                         max_T_rel_dev=float(np.abs(T / ref[:, 1:3] - 1.0).max()))
+    return dict(cells=wl.n_cells, particles=wl.n, steps=steps, oracle_rate_per_step=r_or,
+                **out)
+
+
+def unsorted_entry(ctx, wl_sorted, mode, steps, warmup):
+    """mcc_collide (particles in any order) on the same population in random
+    order, and mcc_bin alone on its ids."""
+    import torch
+    from paper_2407_19151_amd import native, runner
+    wl = wl_sorted.unsorted(seed=77)
+    dw = runner.DeviceWorkload(wl)
+    prec = native.MCC_FP32_KINEMATICS if mode == "fp32" else native.MCC_FP64
+    params = runner.params_for(wl, precision=prec)
+    for k in range(warmup):
+        runner.collide_unsorted(ctx, dw, k, params=params)
+    torch.cuda.synchronize()
+    e0, e1 = events()
+    e0.record()
+    for k in range(steps):
+        runner.collide_unsorted(ctx, dw, warmup + k, params=params)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    for _ in range(warmup):
+        ctx.bin(dw.cells, dw.species, wl.n_cells, wl.n_species)
+    torch.cuda.synchronize()
+    e0, e1 = events()
+    e0.record()
+    for _ in range(steps):
+        ctx.bin(dw.cells, dw.species, wl.n_cells, wl.n_species)
+    e1.record()
+    torch.cuda.synchronize()
+    bms = e0.elapsed_time(e1) / steps
+    assert ctx.device_error() == 0
+    del dw
+    torch.cuda.empty_cache()
+    gbs = BYTES_UNSORTED * wl.n / (ms * 1e-3) / 1e9
+    bgbs = BYTES_BIN * wl.n / (bms * 1e-3) / 1e9
+    return {"ms_per_step": ms, "value": wl.particle_collisions_per_step() / (ms * 1e-3),
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "bytes_per_particle_step": BYTES_UNSORTED},
+            "bin_ms": bms,
+            "bin_roofline": {"bound": "hbm", "achieved": bgbs, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": bgbs / HBM_PEAK_GBS,
+                             "bytes_per_particle": BYTES_BIN}}
+
+
+def per_call_sorted(ctx, wl, mode, steps, warmup):
+    """mcc_collide_sorted called once per step (no plan: the work lists and
+    the weights' data are rebuilt every call)."""
+    import torch
+    from paper_2407_19151_amd import native, runner
+    dw = runner.DeviceWorkload(wl)
+    prec = native.MCC_FP32_KINEMATICS if mode == "fp32" else native.MCC_FP64
+    params = runner.params_for(wl, precision=prec)
+    for k in range(warmup):
+        runner.collide_sorted(ctx, dw, k, params=params, with_stats=False)
+    torch.cuda.synchronize()
+    e0, e1 = events()
+    e0.record()
+    for k in range(steps):
+        runner.collide_sorted(ctx, dw, warmup + k, params=params, with_stats=False)
+    e1.record()
+    torch.cuda.synchronize()
+    del dw
+    torch.cuda.empty_cache()
+    return e0.elapsed_time(e1) / steps
 
 
 def paper_tests(which, steps, warmup):
@@ -416,6 +596,7 @@ def main():
     ctx = native.Context(0)
     out = {}
     modes = ["fp32", "fp64"] if args.only is None else [args.only]
+    tuned_ms = None
     for mode in modes:
         dw = runner.DeviceWorkload(wl)
         prec = native.MCC_FP32_KINEMATICS if mode == "fp32" else native.MCC_FP64
@@ -428,6 +609,13 @@ def main():
         bms = time_buckets(plan, sorted(per_bucket_n), args.steps)
         log("%s per-bucket kernel ms: %s" % (mode, {b: round(v, 4) for b, v in bms.items()}))
         plan.close()
+        if mode == modes[0] and not args.autotune and not args.quick:
+            tplan = runner.make_plan(ctx, dw, params=runner.params_for(wl, precision=prec),
+                                     autotune=True)
+            tuned_ms, _ = time_plan(tplan, args.steps, args.warmup)
+            tuned_desc = json.loads(tplan.describe())
+            tplan.close()
+            log("%s autotuned plan: %.3f ms/step" % (mode, tuned_ms))
         assert ctx.device_error() == 0
         gbs = BYTES_PER_PARTICLE_STEP * wl.n / (ms * 1e-3) / 1e9
         out[mode] = dict(ms=ms, wall=wall, gbs=gbs, value=pcs / (ms * 1e-3), plan=desc,
@@ -445,6 +633,7 @@ def main():
     alg_bytes = BYTES_PER_PARTICLE_STEP * per_bucket_n[dom]
     achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     traffic = read_traffic()
+    valu = read_valu()
     tkey = (head_mode, "%dx%d" % (bd["tpc"], bd["cap"]), "L%d" % bd["layout"])
     res = {
         "metric": "particle-collisions/s per step + HBM roofline fraction, plain FP64 vs FP32+fix",
@@ -474,12 +663,46 @@ def main():
                      "bucket_particles": per_bucket_n[dom], "launch_ms": dom_ms,
                      "algorithmic_bytes_per_launch": alg_bytes,
                      "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP},
+        "valu_roofline": (
+            {"bound": "valu", "achieved": valu[tkey][0] / (dom_ms * 1e-3),
+             "peak": VALU_PEAK_WINST, "unit": "wave-instructions/s",
+             "frac": valu[tkey][0] / (dom_ms * 1e-3) / VALU_PEAK_WINST,
+             "valu_per_launch": valu[tkey][0]}
+            if valu and tkey in valu else None),
         "step_hbm_frac": head["gbs"] / HBM_PEAK_GBS,
         "bucket_launch_ms": {str(BUCKET_CAP[b]): v for b, v in head["bucket_ms"].items()},
     }
     if "fp64" in out and "fp32" in out:
-        res["plain_fp64"] = {"value": out["fp64"]["value"], "ms_per_step": out["fp64"]["ms"],
-                             "step_hbm_frac": out["fp64"]["gbs"] / HBM_PEAK_GBS}
+        o64 = out["fp64"]
+        res["plain_fp64"] = {"value": o64["value"], "ms_per_step": o64["ms"],
+                             "step_hbm_frac": o64["gbs"] / HBM_PEAK_GBS}
+        if valu:
+            # FP64 operations of the plain FP64 step (every bucket kernel, from
+            # the counters) over its step time, against the FP64 vector peak
+            f64 = 0.0
+            for b, bdsc in enumerate(o64["plan"]["buckets"]):
+                if bdsc["cells"] == 0:
+                    continue
+                k = ("fp64", "%dx%d" % (bdsc["tpc"], bdsc["cap"]), "L%d" % bdsc["layout"])
+                f64 += valu[k][1] if k in valu else float("nan")
+            tf = f64 / (o64["ms"] * 1e-3) / 1e12
+            res["plain_fp64"]["fp64_valu"] = {"achieved_tflops": tf, "peak": FP64_PEAK_TFLOPS,
+                                              "frac": tf / FP64_PEAK_TFLOPS}
+    if tuned_ms is not None:
+        res["autotuned_plan"] = {"mode": modes[0], "ms_per_step": tuned_ms,
+                                 "value": pcs / (tuned_ms * 1e-3), "plan": tuned_desc}
+    if not args.quick:
+        log("per-call sorted step (no plan)")
+        pc_ms = per_call_sorted(ctx, wl, head_mode, args.steps, args.warmup)
+        res["per_call_sorted"] = {"mode": head_mode, "ms_per_step": pc_ms,
+                                  "value": pcs / (pc_ms * 1e-3)}
+        log("unsorted entry and binning")
+        res["unsorted_entry"] = dict(unsorted_entry(ctx, wl, head_mode, args.steps, args.warmup),
+                                     mode=head_mode)
+        log("copy ceiling")
+        res["copy_ceiling_gbs"] = copy_ceiling()
+        log("relaxation-rate error against the oracle")
+        res["relaxation_vs_oracle"] = relaxation_rate_error(ctx)
     res["plans"] = {m: o["plan"] for m, o in out.items()}
     if not args.no_cpu:
         log("timing the CPU oracle on a sample")

@@ -305,10 +305,19 @@ mcc_status mcc_collide_adjoint(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t
                                const mcc_params *p, double *g_coulomb_log);
 
 /*
- * Cell binning alone (the grouping used by mcc_collide):
+ * Cell binning alone (the grouping used by mcc_collide, the particles of a
+ * cell of Sec. 2): a stable sort of the particles by the group key
+ * cell * n_species + species.
  *  offsets_out  device int64[n_cells*n_species + 1]
  *  perm_out     device int32[n]: perm_out[j] = original index of the j-th
  *               particle in grouped order (ascending within each group)
+ * A particle whose cell or species id is out of range is latched as data
+ * error 3 and placed after every group, in index order (offsets_out[end]
+ * then counts the particles with valid ids).  Cost: ceil(b/9) passes of a
+ * radix sort over 9-bit digits, b the bits of n_cells * n_species, each
+ * reading and writing 8 B per particle.  Scratch: 16 B per particle plus
+ * 12 B per 4096 particles per digit bin (512 bins), owned by the context.
+ * Errors: MCC_ERR_UNSUPPORTED above 2^31 - 1 particles or groups.
  */
 mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells,
                    const int32_t *species_id, int32_t n_cells,

@@ -40,12 +40,12 @@ hipError_t launch_bucket_cells(const int64_t *offsets, int32_t n_cells, int32_t 
                                int32_t *lists, uint32_t *counts, int32_t *cell_corr, int32_t *err,
                                hipStream_t s);
 int64_t scan_tiles_needed(int64_t m);
-uint64_t canon_scratch_words();
+int64_t bin_tiles(int64_t n);
+int64_t bin_hist_entries(int64_t n);
 hipError_t launch_bin(int64_t n, const int32_t *cells, const int32_t *species, int32_t n_cells,
-                      int32_t S, uint32_t *counts, int64_t *tiles, int64_t *offsets,
-                      unsigned long long *cursor, int32_t *perm, int32_t *big_list,
-                      uint32_t *big_count, uint32_t *canon_scr, int canon_big_grid, int32_t *err,
-                      hipStream_t s);
+                      int32_t S, uint32_t *keys0, uint32_t *keys1, int32_t *vals0,
+                      int32_t *vals1, uint32_t *hist, int64_t *pos, int64_t *tiles,
+                      int64_t *offsets, int32_t *perm, int32_t *err, hipStream_t s);
 hipError_t launch_sample_angles(int method, int precision, int64_t n, const double *s,
                                 const uint32_t *a0, const uint32_t *a1, double *oc, double *st,
                                 double *A, const double2 *tab, hipStream_t st_);
@@ -73,8 +73,6 @@ hipError_t launch_sum_f64(const double *x, int64_t n, double *out, hipStream_t s
 using namespace mcc;
 
 namespace {
-
-constexpr int CANON_BIG_GRID = 16;
 
 struct DevBuf {
   void *p = nullptr;
@@ -148,7 +146,8 @@ struct mcc_ctx {
   // launches of one context must not overlap)
   DevBuf work;
   // unsorted entry
-  DevBuf ucnt, tiles, off, cursor, perm, biglist, bigcount, canon, gw, gx, gy, gz;
+  DevBuf tiles, off, perm, gw, gx, gy, gz;
+  DevBuf bin_k0, bin_k1, bin_v0, bin_v1, bin_hist, bin_pos;  // radix-sort scratch
   // reverse-mode form: per-workgroup scratch (cells up to 4096 particles,
   // and above), per-cell lnL adjoints
   DevBuf adj_small, adj_big, adj_part;
@@ -484,9 +483,9 @@ void mcc_destroy(mcc_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   ctx->big.release();
-  for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->ucnt, &ctx->tiles,
-                    &ctx->off, &ctx->cursor, &ctx->perm, &ctx->biglist, &ctx->bigcount,
-                    &ctx->canon, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97,
+  for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->tiles, &ctx->off, &ctx->perm,
+                    &ctx->bin_k0, &ctx->bin_k1, &ctx->bin_v0, &ctx->bin_v1, &ctx->bin_hist,
+                    &ctx->bin_pos, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97,
                     &ctx->work, &ctx->rb_gold, &ctx->rb_gnew, &ctx->rb_alist, &ctx->rb_flag,
                     &ctx->rb_mpre, &ctx->rb_leave, &ctx->rb_arrive, &ctx->rb_acur,
                     &ctx->rb_cnt, &ctx->rb_aoff, &ctx->rb_rec, &ctx->adj_small, &ctx->adj_big,
@@ -697,19 +696,19 @@ mcc_status mcc_collide_adjoint(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t
 static mcc_status bin_into(mcc_ctx *ctx, int64_t n, const int32_t *cells,
                            const int32_t *species_id, int32_t n_cells, int32_t n_species,
                            int64_t *offsets, int32_t *perm) {
-  const int64_t m = (int64_t)n_cells * n_species;
-  if (!ctx->ucnt.ensure(sizeof(uint32_t) * (size_t)std::max<int64_t>(m, 1)) ||
-      !ctx->tiles.ensure(sizeof(int64_t) * (size_t)scan_tiles_needed(m)) ||
-      !ctx->cursor.ensure(sizeof(unsigned long long) * (size_t)std::max<int64_t>(m, 1)) ||
-      !ctx->biglist.ensure(sizeof(int32_t) * (size_t)std::max<int64_t>(m, 1)) ||
-      !ctx->bigcount.ensure(sizeof(uint32_t) * 4) ||
-      !ctx->canon.ensure(sizeof(uint32_t) * canon_scratch_words() * CANON_BIG_GRID))
+  const size_t nn = (size_t)std::max<int64_t>(n, 1);
+  const int64_t hb = bin_hist_entries(n);  // digit histograms of the tiles
+  if (!ctx->bin_k0.ensure(4 * nn) || !ctx->bin_k1.ensure(4 * nn) ||
+      !ctx->bin_v0.ensure(4 * nn) || !ctx->bin_v1.ensure(4 * nn) ||
+      !ctx->bin_hist.ensure(sizeof(uint32_t) * (size_t)hb) ||
+      !ctx->bin_pos.ensure(sizeof(int64_t) * (size_t)(hb + 1)) ||
+      !ctx->tiles.ensure(sizeof(int64_t) * (size_t)scan_tiles_needed(hb)))
     return MCC_ERR_OOM;
-  return from_hip(launch_bin(n, cells, species_id, n_cells, n_species, ctx->ucnt.as<uint32_t>(),
-                             ctx->tiles.as<int64_t>(), offsets,
-                             ctx->cursor.as<unsigned long long>(), perm,
-                             ctx->biglist.as<int32_t>(), ctx->bigcount.as<uint32_t>(),
-                             ctx->canon.as<uint32_t>(), CANON_BIG_GRID, ctx->err, ctx->stream));
+  return from_hip(launch_bin(n, cells, species_id, n_cells, n_species,
+                             ctx->bin_k0.as<uint32_t>(), ctx->bin_k1.as<uint32_t>(),
+                             ctx->bin_v0.as<int32_t>(), ctx->bin_v1.as<int32_t>(),
+                             ctx->bin_hist.as<uint32_t>(), ctx->bin_pos.as<int64_t>(),
+                             ctx->tiles.as<int64_t>(), offsets, perm, ctx->err, ctx->stream));
 }
 
 mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int32_t *species_id,
@@ -717,7 +716,8 @@ mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int32_t 
   if (!ctx || n < 0 || n_cells < 0 || n_species < 1 || n_species > MCC_MAX_SPECIES ||
       !offsets_out || (n > 0 && (!cells || !species_id || !perm_out)))
     return MCC_ERR_INVALID;
-  if (n > (int64_t)INT32_MAX) return MCC_ERR_UNSUPPORTED;
+  if (n > (int64_t)INT32_MAX || (int64_t)n_cells * n_species > (int64_t)INT32_MAX)
+    return MCC_ERR_UNSUPPORTED;
   HIP_TRY(hipSetDevice(ctx->device));
   mcc_status st = bin_into(ctx, n, cells, species_id, n_cells, n_species, offsets_out, perm_out);
   if (st != MCC_OK) return st;
@@ -821,6 +821,7 @@ mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int3
   if (st != MCC_OK) return st;
   HIP_TRY(hipSetDevice(ctx->device));
   const int64_t m = (int64_t)n_cells * n_species;
+  if (m > (int64_t)INT32_MAX) return MCC_ERR_UNSUPPORTED;
   const size_t nn = (size_t)std::max<int64_t>(n, 1);
   if (!ctx->off.ensure(sizeof(int64_t) * (size_t)(m + 1)) ||
       !ctx->perm.ensure(sizeof(int32_t) * nn) || !ctx->gw.ensure(sizeof(double) * nn) ||

@@ -74,22 +74,6 @@ __global__ void k_bucket_cells(const int64_t *offsets, int32_t n_cells, int32_t 
   }
 }
 
-// ----------------------------------------------------------------------------
-// Binning (unsorted entry)
-// ----------------------------------------------------------------------------
-__global__ void k_bin_count(int64_t n, const int32_t *cells, const int32_t *species,
-                            int32_t n_cells, int32_t S, uint32_t *counts, int32_t *err) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = cells[i], s = species[i];
-    if (c < 0 || c >= n_cells || s < 0 || s >= S) {
-      atomicCAS(err, 0, 3);
-      continue;
-    }
-    atomicAdd(&counts[(int64_t)c * S + s], 1u);
-  }
-}
-
 // three-phase scan of u32 counts into int64 offsets (offsets[m] = total)
 constexpr int SCAN_TPB = 256, SCAN_PPT = 8, SCAN_TILE = SCAN_TPB * SCAN_PPT;
 
@@ -166,102 +150,188 @@ __global__ void k_scan_apply(const uint32_t *in, int64_t m, const int64_t *tile_
   if (base <= m - 1 && m - 1 < base + SCAN_PPT) out[m] = run;  // the total
 }
 
-// unstable placement of original indices; cursor starts as a copy of offsets
-__global__ void k_bin_place(int64_t n, const int32_t *cells, const int32_t *species,
-                            int32_t n_cells, int32_t S, unsigned long long *cursor,
-                            int32_t *perm) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t c = cells[i], s = species[i];
-    if (c < 0 || c >= n_cells || s < 0 || s >= S) continue;
-    const unsigned long long pos = atomicAdd(&cursor[(int64_t)c * S + s], 1ull);
-    if ((int64_t)pos < n) perm[pos] = (int32_t)i;
-  }
+// ----------------------------------------------------------------------------
+// Binning (unsorted entry): a stable LSD radix sort of the group keys
+// g = cell * S + species, 9 bits per pass (two passes up to 2^18 groups).  Each wave owns a tile of
+// RADIX_ROWS rows of 64 consecutive particles.  Per pass: the tiles' digit
+// histograms (digit-major, so one scan gives every (digit, tile) its first
+// output position), the scan, and a scatter in which a particle's rank
+// among the equal digits of its row comes from ballots over the digit bits,
+// rows taken in order: the pass is stable, and no global atomics are used.
+// A particle with an id out of range takes the key m (after every group),
+// so it sorts to the end; the group offsets then come from the boundaries
+// of the sorted keys.
+// ----------------------------------------------------------------------------
+constexpr int RADIX_BITS = 9, RADIX_BINS = 1 << RADIX_BITS;
+constexpr int RADIX_WPB = 4;                      // waves per workgroup (one tile)
+constexpr int RADIX_ROWS = 16;                    // rows of 64 particles per wave
+constexpr int RADIX_TILE = RADIX_WPB * RADIX_ROWS * WAVE;  // 4096 particles
+static_assert(RADIX_BINS % (RADIX_WPB * WAVE) == 0, "digits per thread");
+
+__device__ __forceinline__ uint32_t bin_key(const int32_t *cells, const int32_t *species,
+                                            int64_t i, int32_t n_cells, int32_t S,
+                                            uint32_t m) {
+  const int32_t c = cells[i], sp = species[i];
+  return (c < 0 || c >= n_cells || sp < 0 || sp >= S) ? m
+                                                       : (uint32_t)c * (uint32_t)S + (uint32_t)sp;
 }
 
-__global__ void k_copy_i64_u64(const int64_t *in, unsigned long long *out, int64_t m) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m;
-       i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = (unsigned long long)in[i];
-}
-
-// Canonical (ascending original index) order inside every (cell, species)
-// group: a bucket-rank sort of the group's indices.  Groups larger than CAP
-// are appended to a list for the large-group form, which runs one wave per
-// group on global scratch (one wave keeps every exchange in program order).
-template <int TPC, int CAP, bool G>
-__global__ void __launch_bounds__(TPC) k_bin_canon(const int64_t *offsets, int64_t m,
-                                                   int32_t *perm, int32_t *big_list,
-                                                   uint32_t *big_count, const int32_t *list,
-                                                   const uint32_t *list_count, uint32_t *gscr,
-                                                   uint64_t gstride) {
-  constexpr int PPT = CAP / TPC;
-  static_assert(!G || TPC == WAVE, "the global form runs one wave per group");
-  __shared__ uint32_t wsum[TPC / WAVE];
-  __shared__ uint32_t maxocc;
-  __shared__ uint64_t mm[2 * 2 * (TPC / WAVE)];
-  // the bucket counters are LDS in both forms (global atomics complete in L2
-  // and later plain loads could hit stale L1 lines)
-  __shared__ uint32_t cnt[CAP + 1];
-  uint32_t *vals, *slot = nullptr;
-  uint16_t *mem, *out;
-  if constexpr (!G) {
-    __shared__ uint32_t lv[CAP];
-    __shared__ uint16_t lm[CAP], lo[CAP];
-    vals = lv;
-    mem = lm;
-    out = lo;
+// digit histogram of every tile: hist[d * T + tile]
+template <bool FIRST>
+__global__ void __launch_bounds__(RADIX_WPB * WAVE)
+    k_radix_hist(int64_t n, const int32_t *cells, const int32_t *species, int32_t n_cells,
+                 int32_t S, uint32_t m, const uint32_t *keys, int shift, int64_t T,
+                 uint32_t *hist, int32_t *err) {
+  constexpr int TPB = RADIX_WPB * WAVE, DPT = RADIX_BINS / TPB;  // digits per thread
+  __shared__ uint32_t h[RADIX_BINS];
+  const int t = threadIdx.x;
+  const int64_t tile = blockIdx.x;
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) h[t + j * TPB] = 0u;
+  __syncthreads();
+  const int64_t base = tile * RADIX_TILE;
+  int bad = 0;
+  auto add = [&](uint32_t k) {
+    if (FIRST && k == m) bad = 1;
+    atomicAdd(&h[(k >> shift) & (RADIX_BINS - 1)], 1u);
+  };
+  if (!FIRST && base + RADIX_TILE <= n) {
+    // a whole tile: four keys per load (order does not matter here)
+    const uint4 *k4 = reinterpret_cast<const uint4 *>(keys + base);
+    for (int j = t; j < RADIX_TILE / 4; j += TPB) {
+      const uint4 q = k4[j];
+      add(q.x);
+      add(q.y);
+      add(q.z);
+      add(q.w);
+    }
   } else {
-    uint32_t *g = gscr + (uint64_t)blockIdx.x * gstride;
-    vals = g;
-    slot = g + CAP;
-    mem = reinterpret_cast<uint16_t *>(g + 2 * CAP);
-    out = mem + CAP;
+    for (int j = t; j < RADIX_TILE; j += TPB) {
+      const int64_t i = base + j;
+      if (i < n) add(FIRST ? bin_key(cells, species, i, n_cells, S, m) : keys[i]);
+    }
   }
-  const int64_t ngroups = G ? (int64_t)*list_count : m;
-  for (int64_t gi = blockIdx.x; gi < ngroups; gi += gridDim.x) {
-    const int64_t g = G ? (int64_t)list[gi] : gi;
-    const int64_t b0 = offsets[g], b1 = offsets[g + 1];
-    const int64_t len = b1 - b0;
-    if (len <= 1) continue;
-    if (len > CAP) {
-      if (!G && threadIdx.x == 0) {
-        const uint32_t p = atomicAdd(big_count, 1u);
-        big_list[p] = (int32_t)g;
+  if (FIRST && bad) atomicCAS(err, 0, 3);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) hist[(int64_t)(t + j * TPB) * T + tile] = h[t + j * TPB];
+}
+
+// Stable scatter of (key, value) by the digit; pos[d * T + tile] is the
+// first output position of the tile's digit d (scan of the histograms).
+// The tile is first sorted by digit in LDS -- wave w ranks its 16 rows in
+// order (ballots over the digit bits give a particle's rank among the
+// equal digits of its row), the per-(digit, wave) counts are scanned --
+// then written out along the sorted order, so every digit's run of the
+// tile goes to consecutive addresses.
+template <bool FIRST>
+__global__ void __launch_bounds__(RADIX_WPB * WAVE)
+    k_radix_scatter(int64_t n, const int32_t *cells, const int32_t *species, int32_t n_cells,
+                    int32_t S, uint32_t m, const uint32_t *keys_in, const int32_t *vals_in,
+                    int shift, int64_t T, const int64_t *pos, uint32_t *keys_out,
+                    int32_t *vals_out) {
+  __shared__ uint32_t cnt[RADIX_WPB][RADIX_BINS];  // per wave: its digit counts
+  __shared__ uint32_t lbase[RADIX_BINS];           // first local slot of each digit
+  __shared__ uint32_t gsum[RADIX_WPB];
+  __shared__ uint32_t lk[RADIX_TILE];
+  __shared__ int32_t lv[RADIX_TILE];
+  const int t = threadIdx.x, wv = t / WAVE, lane = t & (WAVE - 1);
+  const int64_t tile = blockIdx.x;
+  const int64_t base = tile * RADIX_TILE;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int d = lane; d < RADIX_BINS; d += WAVE) cnt[wv][d] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  uint32_t rk[RADIX_ROWS];  // rank of the lane's particle among its wave's equal digits
+  uint32_t ky[RADIX_ROWS];
+  int32_t vl[RADIX_ROWS];
+#pragma unroll
+  for (int r = 0; r < RADIX_ROWS; ++r) {
+    const int64_t i = base + (int64_t)(wv * RADIX_ROWS + r) * WAVE + lane;
+    const bool act = i < n;
+    uint32_t k = 0u;
+    int32_t v = 0;
+    if (act) {
+      if constexpr (FIRST) {
+        k = bin_key(cells, species, i, n_cells, S, m);
+        v = (int32_t)i;
+      } else {
+        k = keys_in[i];
+        v = vals_in[i];
       }
-      continue;
     }
-    const int n = (int)len;
-    uint64_t lo[1] = {~0ull}, hi[1] = {0ull};
-    for (int i = threadIdx.x; i < n; i += TPC) {
-      const uint32_t v = (uint32_t)perm[b0 + i];
-      vals[i] = v;
-      lo[0] = v < lo[0] ? v : lo[0];
-      hi[0] = v > hi[0] ? v : hi[0];
+    const uint32_t d = (k >> shift) & (RADIX_BINS - 1);
+    uint64_t eq = __ballot(act);
+#pragma unroll
+    for (int b = 0; b < RADIX_BITS; ++b) {
+      const uint64_t bb = __ballot((d >> b) & 1u);
+      eq &= ((d >> b) & 1u) ? bb : ~bb;
     }
-    block_minmax_u64<TPC, 1>(lo, hi, mm);
-    __syncthreads();
-    const double scale = (double)n / ((double)(hi[0] - lo[0]) + 1.0);
-    const uint64_t vlo = lo[0];
-    bucket_rank_sort<TPC, PPT, G>(
-        n, cnt, mem, out, wsum, &maxocc,
-        [&](int i) -> uint32_t {
-          const uint32_t k = (uint32_t)((double)(vals[i] - vlo) * scale);
-          return k < (uint32_t)n ? k : (uint32_t)(n - 1);
-        },
-        [&](int o, int i) -> bool { return vals[o] < vals[i]; }, slot);
-    for (int i = threadIdx.x; i < n; i += TPC) perm[b0 + i] = (int32_t)vals[out[i]];
-    __syncthreads();
+    rk[r] = act ? cnt[wv][d] + (uint32_t)__popcll(eq & lt) : 0u;
+    ky[r] = k;
+    vl[r] = v;
+    // (every lane has read the count before the leader of its digit advances it)
+    __builtin_amdgcn_wave_barrier();
+    if (act && (eq & lt) == 0ull) cnt[wv][d] += (uint32_t)__popcll(eq);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // digit totals of the tile and their exclusive scan (thread t owns the
+  // DPT consecutive digits from DPT t)
+  constexpr int TPB = RADIX_WPB * WAVE, DPT = RADIX_BINS / TPB;
+  uint32_t tot[DPT], sum = 0;
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    tot[j] = 0;
+#pragma unroll
+    for (int w = 0; w < RADIX_WPB; ++w) tot[j] += cnt[w][DPT * t + j];
+    sum += tot[j];
+  }
+  uint32_t gt;
+  uint32_t run = block_excl_scan1<TPB, false>(sum, gsum, gt);
+#pragma unroll
+  for (int j = 0; j < DPT; ++j) {
+    const int d = DPT * t + j;
+    lbase[d] = run;
+    // each wave's first slot within the digit
+#pragma unroll
+    for (int w = 0; w < RADIX_WPB; ++w) {
+      const uint32_t c = cnt[w][d];
+      cnt[w][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RADIX_ROWS; ++r) {
+    const int64_t i = base + (int64_t)(wv * RADIX_ROWS + r) * WAVE + lane;
+    if (i < n) {
+      const uint32_t d = (ky[r] >> shift) & (RADIX_BINS - 1);
+      const uint32_t slot = cnt[wv][d] + rk[r];
+      lk[slot] = ky[r];
+      lv[slot] = vl[r];
+    }
+  }
+  __syncthreads();
+  const int64_t tn = n - base < RADIX_TILE ? n - base : RADIX_TILE;
+  for (int j = t; j < tn; j += RADIX_WPB * WAVE) {
+    const uint32_t k = lk[j];
+    const uint32_t d = (k >> shift) & (RADIX_BINS - 1);
+    const int64_t g = pos[(int64_t)d * T + tile] + (j - (int64_t)lbase[d]);
+    keys_out[g] = k;
+    vals_out[g] = lv[j];
   }
 }
 
-template __global__ void k_bin_canon<256, 4096, false>(const int64_t *, int64_t, int32_t *,
-                                                       int32_t *, uint32_t *, const int32_t *,
-                                                       const uint32_t *, uint32_t *, uint64_t);
-template __global__ void k_bin_canon<64, MCC_MAX_CELL, true>(const int64_t *, int64_t,
-                                                             int32_t *, int32_t *, uint32_t *,
-                                                             const int32_t *, const uint32_t *,
-                                                             uint32_t *, uint64_t);
+// group offsets from the sorted keys: offsets[g] = first position whose key
+// is >= g (keys above m - 1 mark particles with bad ids, at the end)
+__global__ void k_bin_bounds(int64_t n, const uint32_t *keys, uint32_t m, int64_t *offsets) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t kp = i == 0 ? -1 : (int64_t)keys[i - 1];
+    const int64_t k = i == n ? (int64_t)m : ((int64_t)keys[i] < (int64_t)m ? keys[i] : m);
+    for (int64_t g = kp + 1; g <= k; ++g) offsets[g] = i;
+  }
+}
 
 __global__ void k_gather(int64_t n, const int32_t *perm, const double *w, const double *vx,
                          const double *vy, const double *vz, double *gw, double *gx, double *gy,
@@ -386,36 +456,52 @@ hipError_t launch_scan(const uint32_t *counts, int64_t m, int64_t *tiles, int64_
 
 int64_t scan_tiles_needed(int64_t m) { return (m + SCAN_TILE - 1) / SCAN_TILE + 1; }
 
+// scratch of launch_bin: two key and two value buffers of n u32, the tiles'
+// digit histograms and their scanned positions
+int64_t bin_tiles(int64_t n) { return (n + RADIX_TILE - 1) / RADIX_TILE; }
+// entries of the digit histograms (and of their scanned positions, + 1)
+int64_t bin_hist_entries(int64_t n) {
+  const int64_t T = bin_tiles(n);
+  return (int64_t)RADIX_BINS * (T > 0 ? T : 1);
+}
+
 hipError_t launch_bin(int64_t n, const int32_t *cells, const int32_t *species, int32_t n_cells,
-                      int32_t S, uint32_t *counts, int64_t *tiles, int64_t *offsets,
-                      unsigned long long *cursor, int32_t *perm, int32_t *big_list,
-                      uint32_t *big_count, uint32_t *canon_scr, int canon_big_grid, int32_t *err,
-                      hipStream_t s) {
-  const int64_t m = (int64_t)n_cells * S;
-  hipError_t e = launch_fill_u32(counts, 0u, m, s);
-  if (e != hipSuccess) return e;
-  if (n > 0)
-    hipLaunchKernelGGL(k_bin_count, dim3(grid_for(n, 256)), dim3(256), 0, s, n, cells, species,
-                       n_cells, S, counts, err);
-  e = launch_scan(counts, m, tiles, offsets, s);
-  if (e != hipSuccess) return e;
-  if (m > 0)
-    hipLaunchKernelGGL(k_copy_i64_u64, dim3(grid_for(m, 256)), dim3(256), 0, s, offsets, cursor,
-                       m);
-  if (n > 0)
-    hipLaunchKernelGGL(k_bin_place, dim3(grid_for(n, 256)), dim3(256), 0, s, n, cells, species,
-                       n_cells, S, cursor, perm);
-  e = launch_fill_u32(big_count, 0u, 1, s);
-  if (e != hipSuccess) return e;
-  if (m > 0) {
-    const int g = m < 65536 ? (int)m : 65536;
-    hipLaunchKernelGGL((k_bin_canon<256, 4096, false>), dim3(g), dim3(256), 0, s, offsets, m,
-                       perm, big_list, big_count, (const int32_t *)nullptr,
-                       (const uint32_t *)nullptr, (uint32_t *)nullptr, (uint64_t)0);
-    hipLaunchKernelGGL((k_bin_canon<64, MCC_MAX_CELL, true>), dim3(canon_big_grid), dim3(64),
-                       0, s, offsets, m, perm, big_list, big_count, (const int32_t *)big_list,
-                       (const uint32_t *)big_count, canon_scr, (uint64_t)(3 * MCC_MAX_CELL));
+                      int32_t S, uint32_t *keys0, uint32_t *keys1, int32_t *vals0,
+                      int32_t *vals1, uint32_t *hist, int64_t *pos, int64_t *tiles,
+                      int64_t *offsets, int32_t *perm, int32_t *err, hipStream_t s) {
+  const uint32_t m = (uint32_t)((int64_t)n_cells * S);
+  int bits = 1;
+  while (bits < 32 && (m >> bits) != 0u) ++bits;  // keys run up to m (the bad-id key)
+  const int passes = (bits + RADIX_BITS - 1) / RADIX_BITS;
+  const int64_t T = bin_tiles(n);
+  uint32_t *kb[2] = {keys0, keys1};
+  int32_t *vb[2] = {vals0, vals1};
+  if (n > 0) {
+    const int grid = (int)T;
+    for (int p = 0; p < passes; ++p) {
+      const int shift = p * RADIX_BITS;
+      const uint32_t *kin = p ? kb[(p - 1) & 1] : nullptr;
+      const int32_t *vin = p ? vb[(p - 1) & 1] : nullptr;
+      uint32_t *kout = kb[p & 1];
+      int32_t *vout = p == passes - 1 ? perm : vb[p & 1];
+      if (p == 0)
+        hipLaunchKernelGGL(k_radix_hist<true>, dim3(grid), dim3(RADIX_WPB * WAVE), 0, s, n,
+                           cells, species, n_cells, S, m, kin, shift, T, hist, err);
+      else
+        hipLaunchKernelGGL(k_radix_hist<false>, dim3(grid), dim3(RADIX_WPB * WAVE), 0, s, n,
+                           cells, species, n_cells, S, m, kin, shift, T, hist, err);
+      hipError_t e = launch_scan(hist, (int64_t)RADIX_BINS * T, tiles, pos, s);
+      if (e != hipSuccess) return e;
+      if (p == 0)
+        hipLaunchKernelGGL(k_radix_scatter<true>, dim3(grid), dim3(RADIX_WPB * WAVE), 0, s, n,
+                           cells, species, n_cells, S, m, kin, vin, shift, T, pos, kout, vout);
+      else
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3(grid), dim3(RADIX_WPB * WAVE), 0, s, n,
+                           cells, species, n_cells, S, m, kin, vin, shift, T, pos, kout, vout);
+    }
   }
+  hipLaunchKernelGGL(k_bin_bounds, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, n,
+                     kb[(passes - 1) & 1], m, offsets);
   return hipGetLastError();
 }
 
@@ -436,8 +522,6 @@ hipError_t launch_sample_angles(int method, int precision, int64_t n, const doub
                        method, n, s, a0, a1, oc, st, A, tab);
   return hipGetLastError();
 }
-
-uint64_t canon_scratch_words() { return 3ull * MCC_MAX_CELL; }
 
 hipError_t launch_gather(int64_t n, const int32_t *perm, const double *w, const double *vx,
                          const double *vy, const double *vz, double *gw, double *gx, double *gy,

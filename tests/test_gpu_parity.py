@@ -309,6 +309,37 @@ def test_bin_is_bit_exact(ctx):
     assert np.array_equal(perm.cpu().numpy().astype(np.int64), rp)
 
 
+def test_bin_at_full_size_and_with_bad_ids(ctx):
+    """The radix-sort binning on the 65,536-cell population in random order
+    (2.15e7 particles, two 9-bit passes) equals the oracle's stable
+    counting sort bit for bit; with ids out of range it latches data error 3,
+    groups the valid particles exactly as numpy's stable argsort and puts
+    the bad ones last, in index order."""
+    import torch
+    wl = W.config3().unsorted(seed=9)
+    off, perm = ctx.bin(torch.from_numpy(wl.cells).cuda(), torch.from_numpy(wl.species).cuda(),
+                        wl.n_cells, wl.n_species)
+    assert ctx.device_error() == 0
+    ro, rp = oracle.bin_particles(wl.cells, wl.species, wl.n_cells, wl.n_species)
+    assert np.array_equal(off.cpu().numpy(), ro)
+    assert np.array_equal(perm.cpu().numpy().astype(np.int64), rp)
+    rng = np.random.default_rng(3)
+    n_cells, S, n = 700, 3, 20000
+    cells = rng.integers(0, n_cells, n).astype(np.int32)
+    species = rng.integers(0, S, n).astype(np.int32)
+    cells[::53] = n_cells + 2
+    species[7::101] = -1
+    off, perm = ctx.bin(torch.from_numpy(cells).cuda(), torch.from_numpy(species).cuda(),
+                        n_cells, S)
+    assert ctx.device_error() == 3
+    bad = (cells >= n_cells) | (species < 0)
+    key = np.where(bad, n_cells * S, cells.astype(np.int64) * S + species)
+    assert np.array_equal(perm.cpu().numpy().astype(np.int64), np.argsort(key, kind="stable"))
+    want = np.zeros(n_cells * S + 1, dtype=np.int64)
+    want[1:] = np.cumsum(np.bincount(key[~bad], minlength=n_cells * S))
+    assert np.array_equal(off.cpu().numpy(), want)
+
+
 def test_deterministic_reruns(ctx):
     wl = W.config2(n_cells=24)
     a, _, _ = _gpu_step(ctx, wl, 11)
