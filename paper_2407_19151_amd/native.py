@@ -68,6 +68,19 @@ class MCCError(RuntimeError):
 _lib = None
 
 
+def _hip_runtimes():
+    """Files of the HIP runtime (libamdhip64) mapped into this process."""
+    out = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    out.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return out
+
+
 def load(path: str = LIB_PATH):
     """Load the HIP library; raises if it has not been built."""
     global _lib
@@ -82,6 +95,11 @@ def load(path: str = LIB_PATH):
     # valid here
     import torch  # noqa: F401
     L = C.CDLL(path)
+    runtimes = _hip_runtimes()
+    if len(runtimes) > 1:
+        raise RuntimeError("two HIP runtimes are mapped in this process (%s): this library and "
+                           "torch would hold separate devices, streams and allocations; import "
+                           "torch before loading libmcc_hip.so" % ", ".join(sorted(runtimes)))
     P, i32, i64, u64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
     L.mcc_default_params.argtypes = [C.POINTER(mcc_params)]
     L.mcc_default_params.restype = None

@@ -129,3 +129,50 @@ def test_full_workload_sampled_cells_and_conservation(ctx, full, mode):
     print("  %d sampled cells (%d particles, largest %d): %s"
           % (cells.size, idx.size, int(np.diff(wl.offsets[::wl.n_species])[cells].max()), info),
           flush=True)
+
+
+def test_sharded_calls_equal_one_call(ctx, full):
+    """Cells are independent and every random number is keyed by the global
+    cell id and the particle's index in its cell, so a population split into
+    cell ranges (here 4, balanced by particle count) and stepped in separate
+    calls gives the one-call result bit for bit.  A shard passes its own
+    particles with the full-length offsets array, in which the cells of the
+    other shards are empty (they are bucketed out and cost nothing); this is
+    how a rank of a multi-GPU run would call the library."""
+    import torch
+    from paper_2407_19151_amd import native, runner
+    wl = full
+    S = wl.n_species
+    params = runner.params_for(wl, precision=native.MCC_FP32_KINEMATICS)
+    one = runner.DeviceWorkload(wl)
+    runner.collide_sorted(ctx, one, FIRST_STEP, params=params)
+    v_one = one.velocities()
+    st_one = native.read_stats(one.stats)
+    cc_one = one.cell_corr.cpu().numpy()
+    del one
+    cell_start = wl.offsets[::S]
+    bounds = np.searchsorted(cell_start, np.linspace(0, wl.n, 5)[1:-1])
+    ranges = list(zip(np.r_[0, bounds], np.r_[bounds, wl.n_cells]))
+    v_sh = np.zeros_like(v_one)
+    pairs = 0
+    cc_sh = np.zeros(wl.n_cells, dtype=np.int32)
+    for c0, c1 in ranges:
+        p0, p1 = int(wl.offsets[c0 * S]), int(wl.offsets[c1 * S])
+        print("shard cells [%d, %d) particles [%d, %d)" % (c0, c1, p0, p1), flush=True)
+        sub = wl.copy()
+        sub.offsets = np.clip(wl.offsets - p0, 0, p1 - p0)
+        for k in ("cells", "species", "w", "vx", "vy", "vz"):
+            setattr(sub, k, getattr(wl, k)[p0:p1].copy())
+        dw = runner.DeviceWorkload(sub)
+        runner.collide_sorted(ctx, dw, FIRST_STEP, params=params)
+        v_sh[:, p0:p1] = dw.velocities()
+        pairs += native.read_stats(dw.stats)["pairs"]
+        cc = dw.cell_corr.cpu().numpy()
+        cc_sh[c0:c1] = cc[c0:c1]
+        assert np.all(cc[:c0] == 0) and np.all(cc[c1:] == 0)
+        del dw
+        torch.cuda.empty_cache()
+    assert ctx.device_error() == 0
+    assert np.array_equal(v_sh, v_one)
+    assert pairs == st_one["pairs"]
+    assert np.array_equal(cc_sh, cc_one)
