@@ -224,6 +224,30 @@ mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells,
                               int32_t *cell_corr_pairs);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The step
+ * of mcc_collide_sorted (same arguments, same results bit for bit) with its
+ * cell work lists and size-bucket counters in a fixed device array of the
+ * library instead of context workspace; it calls no hipMalloc, hipFree or
+ * allocating routine (the context, created beforehand, supplies its error
+ * word, angle table and queue counters, all allocated by mcc_create).
+ * Limits: n_cells <= 262144 (MCC_ERR_INVALID above); cells of at most 4096
+ * particles: a larger cell is left unchanged and latched as data error 2;
+ * non-relativistic forms only (MCC_ERR_UNSUPPORTED).  The array (7.3 MB)
+ * exists once per device, is held until the process ends and keeps the
+ * last call's contents; every call on a device shares it, so calls that
+ * overlap on one device race (as calls of one context must not overlap).
+ */
+mcc_status mcc_collide_sorted_noalloc(mcc_ctx *ctx, int64_t n, int32_t n_cells,
+                                      int32_t n_species, const int64_t *offsets,
+                                      const double *weights, double *vx, double *vy, double *vz,
+                                      const double *cell_volume, double cell_volume_scalar,
+                                      const mcc_species *species, int32_t n_coll,
+                                      const mcc_collision *coll, double dt, double coulomb_log,
+                                      uint64_t seed, uint64_t step, const mcc_params *p,
+                                      mcc_stats *stats, int32_t *cell_corr_pairs);
+
+/*
  * One step on particles in any order: cells, species_id are device
  * int32[n].  Particles are grouped by (cell, species) keeping ascending
  * index order inside each group, the sorted step is applied, and the

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -36,6 +37,8 @@ hipError_t launch_zero_stats(mcc_stats *st, hipStream_t s);
 hipError_t launch_check_weights(int64_t n, const double *w, int32_t *err, hipStream_t s);
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s);
 hipError_t launch_inc_u64(uint64_t *p, hipStream_t s);
+hipError_t launch_flag_nonzero(const uint32_t *count, int32_t code, int32_t *err,
+                               hipStream_t s);
 hipError_t launch_bucket_cells(const int64_t *offsets, int32_t n_cells, int32_t S, int64_t n,
                                int32_t *lists, uint32_t *counts, int32_t *cell_corr, int32_t *err,
                                hipStream_t s);
@@ -419,6 +422,41 @@ const char *mcc_status_string(mcc_status s) {
   return "unknown status";
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free step: the size-bucket counters
+// (256 B) and the cell work lists of up to NOALLOC_MAX_CELLS cells.  Each
+// device holds its own copy at its own address; host code reaches it only
+// through the address hipGetSymbolAddress returns for that device.
+// ---------------------------------------------------------------------------
+constexpr int32_t NOALLOC_MAX_CELLS = 1 << 18;
+constexpr size_t NOALLOC_BYTES = 256 + sizeof(int32_t) * (size_t)NBUCKET * NOALLOC_MAX_CELLS;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+void *g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+hipError_t g_noalloc_rc[NOALLOC_MAX_DEVICES] = {};
+bool g_noalloc_done[NOALLOC_MAX_DEVICES] = {};
+
+// once per device, with that device current
+void noalloc_setup(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (g_noalloc_done[device]) return;
+  void *p = nullptr;
+  g_noalloc_rc[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  g_noalloc_ptr[device] = g_noalloc_rc[device] == hipSuccess ? p : nullptr;
+  g_noalloc_done[device] = true;
+}
+
+void *noalloc_ptr(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  return g_noalloc_done[device] ? g_noalloc_ptr[device] : nullptr;
+}
+}  // namespace
+
 mcc_status mcc_create(mcc_ctx **out, int device, void *hip_stream) {
   if (!out) return MCC_ERR_INVALID;
   *out = nullptr;
@@ -436,6 +474,7 @@ mcc_status mcc_create(mcc_ctx **out, int device, void *hip_stream) {
     return from_hip(e);
   }
   ctx->n_cu = prop.multiProcessorCount;
+  noalloc_setup(device);  // (the device is current)
   for (int b = 0; b < NBUCKET; ++b) ctx->variant[b] = -1;  // the mode's default
   const char *val = std::getenv("MCC_VALIDATE");
   ctx->validate = val && val[0] == '1';
@@ -556,6 +595,50 @@ mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t 
   st = launch_buckets(ctx, ctx->big, A, mode_of(p, A), n_cells, ctx->lists.as<int32_t>(),
                       ctx->counts.as<uint32_t>(), ctx->variant, s);
   if (st != MCC_OK) return st;
+  return finish(ctx);
+}
+
+mcc_status mcc_collide_sorted_noalloc(mcc_ctx *ctx, int64_t n, int32_t n_cells,
+                                      int32_t n_species, const int64_t *offsets,
+                                      const double *weights, double *vx, double *vy, double *vz,
+                                      const double *cell_volume, double cell_volume_scalar,
+                                      const mcc_species *species, int32_t n_coll,
+                                      const mcc_collision *coll, double dt, double coulomb_log,
+                                      uint64_t seed, uint64_t step, const mcc_params *p,
+                                      mcc_stats *stats, int32_t *cell_corr_pairs) {
+  if (!ctx || !offsets) return MCC_ERR_INVALID;
+  mcc_status st = check_step(n, n_cells, n_species, weights, vx, vy, vz, cell_volume,
+                             cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, p);
+  if (st != MCC_OK) return st;
+  if (n_cells > NOALLOC_MAX_CELLS) return MCC_ERR_INVALID;
+  if (p->relativistic) return MCC_ERR_UNSUPPORTED;
+  HIP_TRY(hipSetDevice(ctx->device));
+  char *base = static_cast<char *>(noalloc_ptr(ctx->device));
+  if (!base) return MCC_ERR_DEVICE;
+  uint32_t *counts = reinterpret_cast<uint32_t *>(base);
+  int32_t *lists = reinterpret_cast<int32_t *>(base + 256);
+  CollideArgs A;
+  fill_args(A, n, n_cells, n_species, offsets, weights, vx, vy, vz, cell_volume,
+            cell_volume_scalar, species, n_coll, coll, dt, coulomb_log, seed, step, p, stats,
+            cell_corr_pairs, ctx->err, ctx->n97.as<double2>());
+  const int mode = mode_of(p, A);
+  hipStream_t s = ctx->stream;
+  HIP_TRY(launch_fill_u32(counts, 0u, NBUCKET, s));
+  if (stats) HIP_TRY(launch_zero_stats(stats, s));
+  if (n_cells == 0) return finish(ctx);
+  HIP_TRY(launch_check_weights(n, weights, ctx->err, s));
+  HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, lists, counts, cell_corr_pairs,
+                              ctx->err, s));
+  // cells above 4096 particles need the global-scratch kernels: not stepped
+  HIP_TRY(launch_flag_nonzero(counts + (NBUCKET - 1), 2, ctx->err, s));
+  BigScratch none;  // (the variants below never use it)
+  for (int b = NBUCKET - 2; b >= 0; --b) {
+    int v = ctx->variant[b] >= 0 ? ctx->variant[b] : default_variant(mode, b);
+    if (variant_of(mode, v).layout == 2) v = default_variant(mode, b);
+    if (variant_of(mode, v).layout == 2) return MCC_ERR_UNSUPPORTED;
+    st = launch_bucket(ctx, none, A, mode, n_cells, lists, counts, b, v, s);
+    if (st != MCC_OK) return st;
+  }
   return finish(ctx);
 }
 

@@ -41,6 +41,12 @@ __global__ void k_set_u64(uint64_t *p, uint64_t v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// data error `code` when the count of a size bucket is not zero (cells the
+// caller's entry point does not step)
+__global__ void k_flag_nonzero(const uint32_t *count, int32_t code, int32_t *err) {
+  if (threadIdx.x == 0 && *count != 0u) atomicCAS(err, 0, code);
+}
+
 __global__ void k_inc_u64(uint64_t *p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p += 1ull;
 }
@@ -421,6 +427,12 @@ hipError_t launch_zero_stats(mcc_stats *st, hipStream_t s) {
 
 hipError_t launch_set_u64(uint64_t *p, uint64_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_nonzero(const uint32_t *count, int32_t code, int32_t *err,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_flag_nonzero, dim3(1), dim3(64), 0, s, count, code, err);
   return hipGetLastError();
 }
 

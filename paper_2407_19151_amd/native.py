@@ -34,7 +34,7 @@ EXPORTS = ["mcc_default_params", "mcc_status_string", "mcc_create", "mcc_set_str
            "mcc_bin", "mcc_rebin", "mcc_rebin_out", "mcc_plan_create", "mcc_plan_run",
            "mcc_plan_describe",
            "mcc_plan_destroy", "mcc_sample_angles", "mcc_plan_run_bucket",
-           "mcc_collide_sorted_jvp", "mcc_collide_adjoint"]
+           "mcc_collide_sorted_jvp", "mcc_collide_adjoint", "mcc_collide_sorted_noalloc"]
 
 
 class mcc_species(C.Structure):
@@ -119,6 +119,8 @@ def load(path: str = LIB_PATH):
                  f64, f64, u64, u64, C.POINTER(mcc_params), P, P]
     L.mcc_collide_sorted.argtypes = [P, i64, i32, i32, P] + step_args
     L.mcc_collide_sorted.restype = C.c_int
+    L.mcc_collide_sorted_noalloc.argtypes = [P, i64, i32, i32, P] + step_args
+    L.mcc_collide_sorted_noalloc.restype = C.c_int
     L.mcc_collide.argtypes = [P, i64, P, P, i32, i32] + step_args
     L.mcc_collide.restype = C.c_int
     L.mcc_collide_sorted_jvp.argtypes = [P, i64, i32, i32, P, P, P, P, P, P, P, P, P, f64,
@@ -306,6 +308,22 @@ class Context:
             _ptr(vz), cv, cvs, sp, len(collisions), co, float(dt), float(coulomb_log),
             int(seed), int(step), C.byref(p), _ptr(stats), _ptr(cell_corr_pairs))
         _check("mcc_collide_sorted", rc)
+
+    def collide_sorted_noalloc(self, offsets, weights, vx, vy, vz, *, n_cells: int, mass,
+                               charge, collisions, dt: float, coulomb_log: float, seed: int,
+                               step: int, params: Optional[mcc_params] = None,
+                               cell_volume=1.0, stats=None, cell_corr_pairs=None):
+        """mcc_collide_sorted_noalloc: the sorted step with no device allocation."""
+        import torch
+        n, cv, cvs, sp, co, p = self._common(weights, vx, vy, vz, cell_volume, mass, charge,
+                                             collisions, params, stats, cell_corr_pairs, n_cells)
+        _expect(offsets, torch.int64, n_cells * len(mass) + 1, "offsets")
+        self._stream()
+        rc = self.L.mcc_collide_sorted_noalloc(
+            self.h, n, n_cells, len(mass), _ptr(offsets), _ptr(weights), _ptr(vx), _ptr(vy),
+            _ptr(vz), cv, cvs, sp, len(collisions), co, float(dt), float(coulomb_log),
+            int(seed), int(step), C.byref(p), _ptr(stats), _ptr(cell_corr_pairs))
+        _check("mcc_collide_sorted_noalloc", rc)
 
     def collide_sorted_jvp(self, offsets, weights, vx, vy, vz, tx, ty, tz, *, n_cells: int,
                            mass, charge, collisions, dt: float, coulomb_log: float,
