@@ -53,30 +53,44 @@ __global__ void k_inc_u64(uint64_t *p) {
 
 // Work lists: cell c of size n goes to the first bucket whose capacity holds
 // it.  lists[b * n_cells + i], counts[b].  Empty cells get cell_corr = 0.
+// The slots are claimed once per wave and bucket (one atomic for all lanes
+// of the wave that go there, in lane order): a per-cell atomic on seven
+// counters would serialize the whole grid on them.
 __global__ void k_bucket_cells(const int64_t *offsets, int32_t n_cells, int32_t S, int64_t n,
                                int32_t *lists, uint32_t *counts, int32_t *cell_corr,
                                int32_t *err) {
-  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < n_cells;
-       c += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t b0 = offsets[c * S], b1 = offsets[(c + 1) * S];
-    if (b0 < 0 || b1 < b0 || b1 > n) {
-      atomicCAS(err, 0, 1);
-      continue;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < n_cells;
+       c0 += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = c0 + threadIdx.x;
+    int b = -1;  // this lane's bucket, or -1: no list entry
+    if (c < n_cells) {
+      const int64_t b0 = offsets[c * S], b1 = offsets[(c + 1) * S];
+      const int64_t sz = b1 - b0;
+      if (b0 < 0 || b1 < b0 || b1 > n) {
+        atomicCAS(err, 0, 1);
+      } else if (sz == 0) {
+        if (cell_corr) cell_corr[c] = 0;
+      } else {
+        b = 0;
+        while (b < NBUCKET && sz > kBucketCap[b]) ++b;
+        if (b == NBUCKET) {
+          atomicCAS(err, 0, 2);
+          if (cell_corr) cell_corr[c] = 0;
+          b = -1;
+        }
+      }
     }
-    const int64_t sz = b1 - b0;
-    if (sz == 0) {
-      if (cell_corr) cell_corr[c] = 0;
-      continue;
+    for (int k = 0; k < NBUCKET; ++k) {
+      const uint64_t m = __ballot(b == k);
+      if (m == 0) continue;  // (uniform over the wave)
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(&counts[k], (uint32_t)__popcll(m));
+      base = __shfl(base, leader);
+      if (b == k) lists[(int64_t)k * n_cells + base + __popcll(m & below)] = (int32_t)c;
     }
-    int b = 0;
-    while (b < NBUCKET && sz > kBucketCap[b]) ++b;
-    if (b == NBUCKET) {
-      atomicCAS(err, 0, 2);
-      if (cell_corr) cell_corr[c] = 0;
-      continue;
-    }
-    const uint32_t pos = atomicAdd(&counts[b], 1u);
-    lists[(int64_t)b * n_cells + pos] = (int32_t)c;
   }
 }
 

@@ -470,9 +470,12 @@ __device__ __forceinline__ void shuffle_species(const CellMem &M, int ns, int of
     if (i + 2 < ns) key[i + 2] = r.z;
     if (i + 3 < ns) key[i + 3] = r.w;
   }
+  // the sort's bucket counters are cleared under the same barrier
+  for (int i = t; i < ns; i += TPC) cnt[i] = 0u;
+  if (t == 0) *maxocc = 0u;
   __syncthreads();
   const uint64_t nsu = (uint64_t)ns;
-  bucket_rank_sort<TPC, PPT, G>(
+  bucket_rank_sort<TPC, PPT, G, true>(
       ns, cnt, M.mem, out, wsum, maxocc,
       [&](int i) -> uint32_t { return (uint32_t)(((uint64_t)key[i] * nsu) >> 32); },
       [&](int o, int i) -> bool {
@@ -508,9 +511,12 @@ __device__ __forceinline__ void shuffle_two(const CellMem &M, int na, int oa, in
     if (i + 2 < ns) kk[i + 2] = r.z;
     if (i + 3 < ns) kk[i + 3] = r.w;
   }
+  // the sort's bucket counters are cleared under the same barrier
+  for (int i = t; i < n; i += TPC) M.cnt[i] = 0u;
+  if (t == 0) *maxocc = 0u;
   __syncthreads();
   const uint64_t nau = (uint64_t)na, nbu = (uint64_t)nb;
-  bucket_rank_sort<TPC, PPT, G>(
+  bucket_rank_sort<TPC, PPT, G, true>(
       n, M.cnt, M.mem, out, wsum, maxocc,
       [&](int i) -> uint32_t {
         return i < na ? (uint32_t)(((uint64_t)key[i] * nau) >> 32)

@@ -507,9 +507,12 @@ __device__ __forceinline__ uint32_t block_excl_scan1(uint32_t x, uint32_t *wsum,
 // occ_limit: a bucket fuller than this ends the sort right after the
 // counting (out unset): the caller orders such inputs another way, since
 // ranking within a bucket costs its occupancy squared.
+// ZEROED: the caller has set cnt[0..n) and *maxocc to zero before a barrier
+// (saving the sort's own clearing pass and its barrier).
 // Returns the largest bucket occupancy (all threads).
 // ---------------------------------------------------------------------------
-template <int TPC, int PPT, bool G, class BucketF, class LessF, class MapF = IdentityMap>
+template <int TPC, int PPT, bool G, bool ZEROED = false, class BucketF, class LessF,
+          class MapF = IdentityMap>
 __device__ __forceinline__ uint32_t bucket_rank_sort(int n, uint32_t *cnt, uint16_t *mem,
                                                     uint16_t *out, uint32_t *wsum,
                                                     uint32_t *maxocc, BucketF bucket,
@@ -521,9 +524,11 @@ __device__ __forceinline__ uint32_t bucket_rank_sort(int n, uint32_t *cnt, uint1
   // recomputed instead of kept
   const int t = threadIdx.x;
   constexpr int R = G ? 1 : PPT;
-  for (int i = t; i < n; i += TPC) cnt[i] = 0u;
-  if (t == 0) *maxocc = 0u;
-  __syncthreads();
+  if constexpr (!ZEROED) {
+    for (int i = t; i < n; i += TPC) cnt[i] = 0u;
+    if (t == 0) *maxocc = 0u;
+    __syncthreads();
+  }
   uint32_t bk[R], slot[R];
   uint32_t mo = 0;
   if constexpr (G) {

@@ -118,10 +118,13 @@ inline constexpr Variant variant_of(int m, int v) {
 // Minimum waves per SIMD the compiler must leave room for (it then caps the
 // registers, spilling a little): measured on the lognormal cell-size mix,
 // where 2 waves per SIMD (the uncapped allocation) left the cell kernels
-// waiting on LDS and barriers most of the time.  1: no cap (variants whose
-// LDS use already limits residency, the global-scratch and tangent forms).
+// waiting on LDS and barriers most of the time.  Cells of 2048 and 4096
+// particles, whose LDS use allows at most 8 waves per CU, ask for 2: an
+// uncapped allocation that reaches 256 registers leaves room for one.
+// 1: no cap (the global-scratch and tangent forms).
 constexpr int min_waves(int tpc, int cap, int layout, bool fp64, bool tangent) {
-  if (tangent || layout == 2 || cap >= 2048) return 1;
+  if (tangent || layout == 2) return 1;
+  if (cap >= 2048) return 2;
   if (tpc == 64 && cap == 128) return 4;
   return 3;
 }
