@@ -231,18 +231,19 @@ __global__ void __launch_bounds__(TPC) adjoint_kernel(AdjointArgs A) {
       // descending-weight order (as the step computes them per cell)
       for (int sp = 0; sp < S; ++sp) {
         const int o = s_so[sp], ns = s_so[sp + 1] - o;
-        double acc[2] = {0.0, 0.0};
+        CSum<2> acc;  // compensated, as the step sums them
+        acc.zero();
         uint64_t lo[1] = {~0ull}, hi[1] = {0ull};
         for (int e = o + t; e < o + ns; e += TPC) {
           const double we = W[e];
-          acc[0] += we;
-          acc[1] += we * we;
+          acc.add(0, we);
+          acc.add(1, we * we);
           const uint64_t bits = (uint64_t)__double_as_longlong(we);
           lo[0] = bits < lo[0] ? bits : lo[0];
           hi[0] = bits > hi[0] ? bits : hi[0];
         }
         double tot[2];
-        block_sum<TPC, 2>(acc, red, tot);
+        block_csum<TPC, 2>(acc, red, tot);
         block_minmax_u64<TPC, 1>(lo, hi, redu);
         int flag = WORDER_EQUAL;
         if (A.sortw && ns >= 2 && lo[0] != hi[0]) {

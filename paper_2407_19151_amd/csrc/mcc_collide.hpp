@@ -917,18 +917,19 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       // correction order of every collision when no two weights are equal
       for (int sp = 0; sp < S; ++sp) {
         const int o = s_so[sp], ns = s_so[sp + 1] - o;
-        double acc[2] = {0.0, 0.0};
+        CSum<2> acc;  // compensated, as every per-cell moment sum
+        acc.zero();
         uint64_t lo[1] = {~0ull}, hi[1] = {0ull};
         for (int e = o + t; e < o + ns; e += TPC) {
           const double we = M.w[e];
-          acc[0] += we;
-          acc[1] += we * we;
+          acc.add(0, we);
+          acc.add(1, we * we);
           const uint64_t bits = (uint64_t)__double_as_longlong(we);
           lo[0] = bits < lo[0] ? bits : lo[0];
           hi[0] = bits > hi[0] ? bits : hi[0];
         }
         double tot[2];
-        block_sum<TPC, 2>(acc, red, tot);
+        block_csum<TPC, 2>(acc, red, tot);
         block_minmax_u64<TPC, 1>(lo, hi, redu);
         int flag = WORDER_EQUAL;
         if (A.sortw && ns >= 2 && lo[0] != hi[0]) {
@@ -1269,7 +1270,8 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         // inter-species collision, the kinetic energy of each species
         double es = 0.0, ec = 0.0;
         double es1 = 0.0, ec1 = 0.0;  // species b of a dual pass
-        // KE_a, KE_b; tangent form: then the tangents of dE, KE_a, KE_b
+        // KE_a, KE_b (inter-species only: sums of positive terms, plain);
+        // tangent form: then the tangents of dE, KE_a, KE_b
         constexpr int NE = TAN ? 5 : 2;
         double Ev[NE];
 #pragma unroll
@@ -1306,8 +1308,10 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             }
             csum_add(es, ec, (mem && !sb) ? term : 0.0);
             if constexpr (DUAL) csum_add(es1, ec1, (mem && sb) ? term : 0.0);
-            Ev[0] += (mem && isa) ? ke : 0.0;
-            Ev[1] += (mem && !isa) ? ke : 0.0;
+            if (TAN || !intra) {
+              Ev[0] += (mem && isa) ? ke : 0.0;
+              Ev[1] += (mem && !isa) ? ke : 0.0;
+            }
             if constexpr (TAN) {
               const double tvx = M.tx[e], tvy = M.ty[e], tvz = M.tz[e];
               const double dke = mp * (vx * tvx + vy * tvy + vz * tvz);
@@ -1352,8 +1356,12 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
           // two intra-species violations, each corrected on its own species
           block_sum_c2<TPC>(es, ec, es1, ec1, red, dEs0, dEs1);
         } else if (intra) {
-          double tot[1];
-          block_sum_c1<TPC, 1>(es, ec, Ev, red, dEs0, tot);
+          CSum<1> Cv;
+          Cv.s[0] = es;
+          Cv.c[0] = ec;
+          double out[1];
+          block_csum<TPC, 1>(Cv, red, out);
+          dEs0 = out[0];
         } else {
           double tot[2];
           block_sum_c1<TPC, 2>(es, ec, Ev, red, dEs0, tot);

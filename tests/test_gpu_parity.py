@@ -261,6 +261,29 @@ def test_relativistic_one_wave_global_forms(ctx):
     _parity(ctx, wl.copy(), 2, pairing=2)
 
 
+@pytest.mark.parametrize("wmode", ["lognormal", "equal"])
+def test_pairwise_momentum_sums_conserve_at_the_maximum_cell(ctx, wmode):
+    """The momentum sums of Eq. (17) and the species energies of Eq. (24)
+    are plain FP64 per thread and then a pairwise (butterfly) tree, not
+    compensated as the oracle's: at the largest cell (MCC_MAX_CELL
+    particles, 16384 per species) the residual momentum and energy after the
+    correction still sit at FP64 rounding in both kinematics forms, with
+    lognormal weights (rejections leave a large momentum change to restore)
+    and with equal weights (the change to restore is itself rounding noise,
+    so the tree's error and the compensated sum's differ most)."""
+    from paper_2407_19151_amd import native
+    wl = custom_workload([(16384, 16384), (60, 40)], seed=49, weight_mode=wmode)
+    _, sg, so = _parity(ctx, wl.copy(), 1, diagnostics=True)
+    print("  FP64 residuals: dP %.2e dE %.2e (oracle, compensated: %.2e %.2e)"
+          % (sg["max_rel_dP"], sg["max_rel_dE"], so["max_rel_dP"], so["max_rel_dE"]), flush=True)
+    assert sg["max_rel_dP"] < 1e-14 and sg["max_rel_dE"] < 1e-14
+    _, s32, _ = _gpu_step(ctx, wl.copy(), 1, diagnostics=True,
+                          precision=native.MCC_FP32_KINEMATICS)
+    print("  FP32-kinematics residuals: dP %.2e dE %.2e" % (s32["max_rel_dP"], s32["max_rel_dE"]),
+          flush=True)
+    assert s32["max_rel_dP"] < 1e-14 and s32["max_rel_dE"] < 1e-14
+
+
 def test_diagnostics_show_roundoff_conservation(ctx):
     wl = W.config2(n_cells=32)
     _, sg, so = _parity(ctx, wl, 0, diagnostics=True)
