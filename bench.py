@@ -83,6 +83,10 @@ def parse():
                          "sampling T_e and T_i, and exit")
     ap.add_argument("--paper-test3", action="store_true",
                     help="only time the paper's Test 3 cases (SI units, 1600 cells, FP64) and exit")
+    ap.add_argument("--configs", action="store_true",
+                    help="only time the other named workloads at their full sizes (FP64 and "
+                         "FP32 plans; tangent and adjoint steps of the differentiated one) and "
+                         "exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB three times (the "
                          "reference reading for the HBM byte counters) and exit")
@@ -367,6 +371,76 @@ def per_call_sorted(ctx, wl, mode, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
+def config_scale(ctx, steps=10, warmup=2):
+    """The other named workloads at their full sizes, timed as the headline
+    is (plan, one HIP graph per step, inputs resident in HBM): per-step time,
+    particle-collisions per second and the step's algorithmic HBM fraction
+    (64 B per particle), in FP64 and, where the kinematics allow it, FP32.
+    The differentiated workload also times one tangent (forward-mode) step
+    and one adjoint (reverse-mode) step through the C ABI."""
+    import torch
+    from paper_2407_19151_amd import native, runner
+    from paper_2407_19151_amd import workloads as W
+    f64, f32 = native.MCC_FP64, native.MCC_FP32_KINEMATICS
+    cases = [("config1", W.config1, (("fp64", f64), ("fp32", f32))),
+             ("config2_n97", lambda: W.config2(method=W.N97), (("fp64", f64), ("fp32", f32))),
+             ("config2_ta77", lambda: W.config2(method=W.TA77), (("fp64", f64), ("fp32", f32))),
+             ("config4_relativistic", W.config4, (("fp64", f64),)),
+             ("config5", W.config5, (("fp64", f64), ("fp32", f32)))]
+    out = {}
+    for name, make, precs in cases:
+        wl = make()
+        pcs = wl.particle_collisions_per_step()
+        entry = {"workload": wl.name, "cells": wl.n_cells, "particles": wl.n,
+                 "particle_collisions_per_step": pcs}
+        for pname, prec in precs:
+            dw = runner.DeviceWorkload(wl)
+            plan = runner.make_plan(ctx, dw, params=runner.params_for(wl, precision=prec),
+                                    autotune=False)
+            ms, _ = time_plan(plan, steps, warmup)
+            plan.close()
+            entry[pname] = {"ms_per_step": ms, "particle_collisions_per_s": pcs / (ms * 1e-3),
+                            "step_hbm_frac": BYTES_PER_PARTICLE_STEP * wl.n / (ms * 1e-3) / 1e9
+                            / HBM_PEAK_GBS}
+            del dw
+        if name == "config5":
+            for pname, prec in (("fp64", f64), ("fp32", f32)):
+                dw = runner.DeviceWorkload(wl)
+                params = runner.params_for(wl, precision=prec)
+                v = torch.stack([dw.vx, dw.vy, dw.vz]).contiguous()
+                g = torch.randn(3, wl.n, dtype=torch.float64, device="cuda")
+                gl = torch.zeros(1, dtype=torch.float64, device="cuda")
+                for k in range(warmup):
+                    runner.collide_adjoint(ctx, dw, v, g, k, g_lnl=gl, params=params)
+                torch.cuda.synchronize()
+                e0, e1 = events()
+                e0.record()
+                for k in range(steps):
+                    runner.collide_adjoint(ctx, dw, v, g, warmup + k, g_lnl=gl, params=params)
+                e1.record()
+                torch.cuda.synchronize()
+                entry[pname]["adjoint_ms_per_step"] = e0.elapsed_time(e1) / steps
+                if prec == f64:
+                    t = torch.randn(3, wl.n, dtype=torch.float64, device="cuda")
+                    for k in range(warmup):
+                        runner.collide_sorted_jvp(ctx, dw, t, k, update_primal=False)
+                    torch.cuda.synchronize()
+                    e0, e1 = events()
+                    e0.record()
+                    for k in range(steps):
+                        runner.collide_sorted_jvp(ctx, dw, t, warmup + k, update_primal=False)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    entry[pname]["tangent_ms_per_step"] = e0.elapsed_time(e1) / steps
+                del dw
+        assert ctx.device_error() == 0
+        out[name] = entry
+        log("%s: %s" % (name, {k: round(v["ms_per_step"], 4) for k, v in entry.items()
+                               if isinstance(v, dict)}))
+        torch.cuda.empty_cache()
+    return out
+
+
 def paper_tests(which, steps, warmup):
     """Step time and throughput of each case of the paper's Test 1, 2 or 3
     (a plan, graph replays)."""
@@ -572,6 +646,10 @@ def main():
     if args.nxn:
         nxn_bench(args.steps, args.warmup)
         return
+    if args.configs:
+        from paper_2407_19151_amd import native
+        print(json.dumps(config_scale(native.Context(0), args.steps, args.warmup)), flush=True)
+        return
     if args.rebin:
         rebin_bench(args.steps, args.warmup)
         return
@@ -703,6 +781,8 @@ def main():
         res["copy_ceiling_gbs"] = copy_ceiling()
         log("relaxation-rate error against the oracle")
         res["relaxation_vs_oracle"] = relaxation_rate_error(ctx)
+        log("the other workloads at full size")
+        res["config_scale"] = config_scale(ctx)
     res["plans"] = {m: o["plan"] for m, o in out.items()}
     if not args.no_cpu:
         log("timing the CPU oracle on a sample")
