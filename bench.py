@@ -83,6 +83,9 @@ def parse():
                          "sampling T_e and T_i, and exit")
     ap.add_argument("--paper-test3", action="store_true",
                     help="only time the paper's Test 3 cases (SI units, 1600 cells, FP64) and exit")
+    ap.add_argument("--unsorted", action="store_true",
+                    help="only time the unsorted entry (mcc_collide on the 65,536-cell population "
+                         "in random order, FP32 kinematics) and mcc_bin alone, and exit")
     ap.add_argument("--configs", action="store_true",
                     help="only time the other named workloads at their full sizes (FP64 and "
                          "FP32 plans; tangent and adjoint steps of the differentiated one) and "
@@ -645,6 +648,12 @@ def main():
         return
     if args.nxn:
         nxn_bench(args.steps, args.warmup)
+        return
+    if args.unsorted:
+        from paper_2407_19151_amd import native
+        from paper_2407_19151_amd import workloads as W
+        print(json.dumps(unsorted_entry(native.Context(0), W.config3(), "fp32", args.steps,
+                                        args.warmup)), flush=True)
         return
     if args.configs:
         from paper_2407_19151_amd import native

@@ -673,6 +673,11 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   __shared__ double s_sw[MCC_MAX_SPECIES], s_sw2[MCC_MAX_SPECIES];
   __shared__ int s_wflag[MCC_MAX_SPECIES];
   __shared__ unsigned long long s_st[4];  // pairs, correction pairs, failures, collisions
+  // the workgroup's totals of s_st and s_sd over its cells (thread 0), added
+  // to the caller's statistics once at the end: one atomic per cell and
+  // counter would serialize the whole grid on four addresses
+  __shared__ unsigned long long s_acc[4];
+  __shared__ double s_accd[2];
   __shared__ double s_sd[2];              // diagnostics maxima
   __shared__ int s_ncut[2];
   __shared__ double s_res[2];
@@ -806,6 +811,11 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   uint32_t *const qctr = A.work + q * WORK_STRIDE;
   int par = 0;
   // per-species and per-collision constants in LDS (indexed at run time)
+
+  if (t == 0) {
+    for (int i = 0; i < 4; ++i) s_acc[i] = 0ull;
+    s_accd[0] = s_accd[1] = 0.0;
+  }
 
   for (uint32_t li = q + NQ * (blockIdx.x / NQ); li < count;) {
     MCC_PHASE(0);  // header and staging
@@ -1694,18 +1704,9 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
     }
     if (t == 0) {
       if (A.cell_corr) A.cell_corr[cell] = (int32_t)s_st[1];
-      if (A.stats) {
-        atomicAdd(&A.stats->pairs, s_st[0]);
-        if (s_st[1]) atomicAdd(&A.stats->corr_pairs, s_st[1]);
-        if (s_st[2]) atomicAdd(&A.stats->failed, s_st[2]);
-        atomicAdd(&A.stats->collisions, s_st[3]);
-        if (A.diag) {
-          atomicMax(reinterpret_cast<unsigned long long *>(&A.stats->max_rel_dP),
-                    (unsigned long long)__double_as_longlong(s_sd[0]));
-          atomicMax(reinterpret_cast<unsigned long long *>(&A.stats->max_rel_dE),
-                    (unsigned long long)__double_as_longlong(s_sd[1]));
-        }
-      }
+      for (int i = 0; i < 4; ++i) s_acc[i] += s_st[i];
+      s_accd[0] = s_sd[0] > s_accd[0] ? s_sd[0] : s_accd[0];
+      s_accd[1] = s_sd[1] > s_accd[1] ? s_sd[1] : s_accd[1];
     }
     if (t == 0) s_next[par] = q + NQ * (nq + claim);
     __syncthreads();
@@ -1713,6 +1714,18 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
     par ^= 1;
   }
   if (t == 0) {
+    if (A.stats) {
+      if (s_acc[0]) atomicAdd(&A.stats->pairs, s_acc[0]);
+      if (s_acc[1]) atomicAdd(&A.stats->corr_pairs, s_acc[1]);
+      if (s_acc[2]) atomicAdd(&A.stats->failed, s_acc[2]);
+      if (s_acc[3]) atomicAdd(&A.stats->collisions, s_acc[3]);
+      if (A.diag) {
+        atomicMax(reinterpret_cast<unsigned long long *>(&A.stats->max_rel_dP),
+                  (unsigned long long)__double_as_longlong(s_accd[0]));
+        atomicMax(reinterpret_cast<unsigned long long *>(&A.stats->max_rel_dE),
+                  (unsigned long long)__double_as_longlong(s_accd[1]));
+      }
+    }
     // every claim of this workgroup has returned; the last one of its queue
     // resets the queue's counters (all other claims are complete by then)
     if (atomicAdd(qctr + 1, 1u) == nq - 1) {
