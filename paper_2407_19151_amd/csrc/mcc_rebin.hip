@@ -159,13 +159,25 @@ __device__ __forceinline__ void bitonic(int32_t (&v)[N]) {
         }
       }
 }
+// Two kernels: the lists of at most 8 (nearly all of them when a few per cent
+// of the particles move) and the longer ones.  One kernel with both paths
+// kept the 32-entry network's registers for every thread, and its few
+// long lists held whole waves.
 __global__ void k_rebin_sort(int64_t m, const int64_t *aoff, int32_t *alist) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
        g += (int64_t)gridDim.x * blockDim.x) {
     int32_t *a = alist + aoff[g];
     const int64_t k = aoff[g + 1] - aoff[g];
-    if (k < 2) continue;
-    if (k <= 8) {
+    if (k < 2 || k > 8) continue;
+    if (k == 2) {
+      const int32_t x = a[0], y = a[1];
+      if (y < x) {
+        a[0] = y;
+        a[1] = x;
+      }
+      continue;
+    }
+    {
       int32_t v[8];
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = i < k ? a[i] : INT32_MAX;
@@ -178,8 +190,15 @@ __global__ void k_rebin_sort(int64_t m, const int64_t *aoff, int32_t *alist) {
 #pragma unroll
       for (int i = 0; i < 8; ++i)
         if (i < k) a[i] = v[i];
-      continue;
     }
+  }
+}
+__global__ void k_rebin_sort_long(int64_t m, const int64_t *aoff, int32_t *alist) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    int32_t *a = alist + aoff[g];
+    const int64_t k = aoff[g + 1] - aoff[g];
+    if (k <= 8) continue;
     if (k <= 32) {
       int32_t v[32];
 #pragma unroll
@@ -292,6 +311,7 @@ hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const 
     hipLaunchKernelGGL(k_rebin_lists, dim3(grid_of(n)), dim3(256), 0, s, n, gnew, flag, aoff,
                        acur, alist);
     hipLaunchKernelGGL(k_rebin_sort, dim3(grid_of(m)), dim3(256), 0, s, m, aoff, alist);
+    hipLaunchKernelGGL(k_rebin_sort_long, dim3(grid_of(m)), dim3(256), 0, s, m, aoff, alist);
     hipLaunchKernelGGL(k_rebin_groups, dim3(grid_of(m)), dim3(256), 0, s, m, n, off, mpre, aoff,
                        leave, off_new, reinterpret_cast<GroupRec *>(rec));
     hipLaunchKernelGGL(k_rebin_place, dim3(grid_of(n)), dim3(256), 0, s, n, gold, gnew, mpre,
