@@ -112,15 +112,12 @@ def copy_calibration(mib):
 
 
 def kernel_source_hash():
-    """sha256 over the HIP sources: byte counters taken from other sources
-    do not describe the kernels that run now."""
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2407_19151_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
-    return h.hexdigest()
+    """sha256 over the sources the collide kernels are built from (their
+    instantiation units, the headers they include and the public header):
+    counters taken from other sources do not describe the kernels that run
+    now."""
+    from paper_2407_19151_amd import profile_summary
+    return profile_summary.source_hash()
 
 
 def read_traffic():

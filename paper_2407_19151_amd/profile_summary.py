@@ -23,14 +23,23 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 KNAME = re.compile(r"collide_kernel<(\d+), (\d+), (float|double), false, (\d), false, false, 0>")
 
 
+KERNEL_HEADERS = ("mcc_collide.hpp", "mcc_device.hpp", "mcc_kernel_args.hpp", "mcc_variants.hpp")
+
+
 def source_hash() -> str:
-    """sha256 over the HIP sources (the same digest bench.py checks)."""
+    """sha256 over the sources the collide kernels are built from: their
+    instantiation units (mcc_collide_*.hip), the headers those include and
+    the public header (the digest bench.py checks before it reports the
+    counters)."""
     h = hashlib.sha256()
     d = os.path.join(HERE, "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    files = sorted(f for f in os.listdir(d)
+                   if (f.startswith("mcc_collide_") and f.endswith(".hip")) or f in KERNEL_HEADERS)
+    paths = [os.path.join(d, f) for f in files]
+    paths.append(os.path.join(os.path.dirname(HERE), "include", "mcc.h"))
+    for path in paths:
+        h.update(os.path.basename(path).encode())
+        h.update(open(path, "rb").read())
     return h.hexdigest()
 
 
@@ -97,7 +106,8 @@ def traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, commands, copy_k
               "WRITE_SIZE %.0f KiB" % (copy_kib, cf, cw),
               "# bytes = fetch_kib * 1024 * fetch_factor + write_kib * 1024 * write_factor "
               "(averages over all dispatches)",
-              "# bench.py reports these only while source_sha256 matches the HIP sources",
+              "# bench.py reports these only while source_sha256 matches the sources of the collide "
+              "kernels",
               "source_sha256 " + source_hash(),
               "fetch_factor %.4f" % ff, "write_factor %.4f" % wf]
     for k in sorted(f):
