@@ -53,7 +53,7 @@ def test_duplicity_fp32_and_relativistic(ctx):
     vg, _, _ = _gpu_step(ctx, wl, 2, pairing=DUP, precision=native.MCC_FP32_KINEMATICS)
     ref = wl.copy()
     oracle_step(ref, 2, pairing=DUP, uniform23=True)
-    info = check_parity(wl, vg, ref.velocities(), v0, tol=1e-4, cond_tol=0.2)
+    info = check_parity(wl, vg, ref.velocities(), v0, tol=1e-4, cond_tol=1e-4)
     print("fp32 duplicity parity: %s" % info, flush=True)
     wr = custom_workload([(50, 40), (13, 2), (300, 200)], seed=44, masses=(1.0, 1836.0),
                          relativistic=True, c=1.0, dt=0.003)

@@ -125,7 +125,7 @@ def test_full_workload_sampled_cells_and_conservation(ctx, full, mode):
 
     info = check_parity(sub, vg[:, idx], ref.velocities(), sub.velocities(),
                         tol=FP32_TOL if mode == "fp32" else FP64_TOL,
-                        cond_tol=0.2 if mode == "fp32" else 1e-6, rerun=rerun)
+                        cond_tol=FP32_TOL if mode == "fp32" else 1e-6, rerun=rerun)
     print("  %d sampled cells (%d particles, largest %d): %s"
           % (cells.size, idx.size, int(np.diff(wl.offsets[::wl.n_species])[cells].max()), info),
           flush=True)

@@ -363,7 +363,7 @@ def test_global_layout_fp32_matches_the_oracle(ctx, pairing):
         finally:
             ctx.set_variant(6, -1)
         info = check_parity(wl, vg, ref.velocities(), v0, tol=tol,
-                            cond_tol=tol if pairing == NXN else 0.2)
+                            cond_tol=tol)
         print("  against the oracle (tol %.1e): %s" % (tol, info), flush=True)
         for k in ("pairs", "collisions", "failed"):
             assert sg[k] == so[k]

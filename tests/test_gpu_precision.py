@@ -68,7 +68,7 @@ def test_fp32_kinematics_step_parity_and_exact_conservation(ctx, method):
     assert ctx.device_error() == 0
     ref = wl.copy()
     so = oracle_step(ref, 3, uniform23=True)
-    info = check_parity(wl, vg, ref.velocities(), v0, tol=FP32_TOL, cond_tol=0.2)
+    info = check_parity(wl, vg, ref.velocities(), v0, tol=FP32_TOL, cond_tol=FP32_TOL)
     print("fp32 parity:", info, "stats:", st, flush=True)
     assert st["pairs"] == so["pairs"] and st["collisions"] == so["collisions"]
     assert st["failed"] == so["failed"]
@@ -140,7 +140,7 @@ def test_fp32_kinematics_large_cells_match_the_oracle(ctx):
         finally:
             ctx.set_variant(6, -1)
         assert ctx.device_error() == 0
-        info = check_parity(wl, vg, ref.velocities(), v0, tol=FP32_TOL, cond_tol=0.2)
+        info = check_parity(wl, vg, ref.velocities(), v0, tol=FP32_TOL, cond_tol=FP32_TOL)
         print("  fp32 against the oracle: %s" % info, flush=True)
         for k in ("pairs", "collisions", "failed"):
             assert sg[k] == so[k]
