@@ -241,6 +241,29 @@ def cpu_baseline(seconds):
                 break
         dt = time.perf_counter() - t0
         out[threads] = (pc * steps / dt, steps, sub.n)
+    # the other workloads, on every core: whole at their full sizes except the
+    # relativistic beam (its first 1024 of 16384 cells, rates scaled per
+    # particle); each for about a second
+    configs = {}
+    oracle.set_threads(nproc)
+    for name, make in (("config1", W.config1), ("config2_n97", lambda: W.config2(method=W.N97)),
+                       ("config2_ta77", lambda: W.config2(method=W.TA77)),
+                       ("config4_relativistic_1024_cells", lambda: W.config4(n_cells=1024)),
+                       ("config5", W.config5)):
+        wl = make()
+        pc = wl.particle_collisions_per_step()
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            st = oracle.run_workload(wl, steps=1, first_step=steps)
+            steps += 1
+            if time.perf_counter() - t0 > 1.0:
+                break
+        dt = time.perf_counter() - t0
+        configs[name] = dict(particles=wl.n, steps=steps,
+                             particle_collisions_per_s=pc * steps / dt,
+                             particle_steps_per_s=wl.n * steps / dt,
+                             pairs_per_s=st["pairs"] * steps / dt)
     oracle.set_threads(1)
     v1, s1, n1 = out[1]
     va, sa, _ = out[nproc]
@@ -248,7 +271,7 @@ def cpu_baseline(seconds):
                 sample="%d steps (%d threads) and %d steps (1 thread) of the first 2048 cells "
                        "of the same recipe (%d particles, N97, FP64, correction on)"
                        % (sa, nproc, s1, n1),
-                one_thread=v1, nproc=nproc, cpu=model)
+                one_thread=v1, nproc=nproc, cpu=model, configs=configs)
 
 
 def copy_ceiling():
