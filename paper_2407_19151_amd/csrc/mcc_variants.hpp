@@ -65,12 +65,15 @@ constexpr Variant kRelVariant4096Wide = {256, 4096, 2};
 constexpr int NBUCKET = 7;
 constexpr int kBucketCap[NBUCKET] = {128, 256, 512, 1024, 2048, 4096, 32768};
 // default variant per bucket (the fastest measured on lognormal cell-size
-// mixes; the autotuner may pick another candidate): FP32 kinematics take 256
-// threads for the 2048 bucket, FP64 (more registers per thread) 512.  Cells
-// above 4096 particles take 8 waves in global scratch (measured on cells of
-// 4 400 to 8 200 particles: 5.1-5.3x the one-wave variant, 1.5x the 4-wave)
+// mixes; the autotuner may pick another candidate).  The FP32 and FP64 modes
+// take 256 threads for the 2048 bucket (under the 2-wave register cap the
+// FP64 512-thread kernel holds one workgroup per CU: 0.55 against 0.43 ms on
+// the 65,536-cell mix); the relativistic and tangent modes, whose cells keep
+// the full LDS layout, 512.  Cells above 4096 particles take 8 waves in
+// global scratch (measured on cells of 4 400 to 8 200 particles: 5.1-5.3x the
+// one-wave variant, 1.5x the 4-wave)
 constexpr int kDefaultVariant[NBUCKET] = {0, 1, 3, 5, 7, 12, 15};
-constexpr int kDefaultVariantFP32[NBUCKET] = {0, 1, 3, 5, 11, 12, 15};
+constexpr int kDefaultVariantFP[NBUCKET] = {0, 1, 3, 5, 11, 12, 15};
 // candidates the autotuner times per bucket (-1 terminated)
 constexpr int kCandidates[NBUCKET][5] = {
     {0, 1, 2, -1, -1}, {1, 2, 3, 4, -1}, {3, 4, 5, 6, -1}, {5, 6, 7, 11, -1},
@@ -89,8 +92,10 @@ inline constexpr Variant compact_of(Variant V) {
 }
 
 inline constexpr int default_variant(int mode, int bucket) {
-  return (base_mode(mode) == MODE_FP32 || mode == MODE_FP32_DIAG) ? kDefaultVariantFP32[bucket]
-                                                                    : kDefaultVariant[bucket];
+  return (base_mode(mode) == MODE_FP32 || mode == MODE_FP32_DIAG || base_mode(mode) == MODE_FP64 ||
+          mode == MODE_FP64_DIAG)
+             ? kDefaultVariantFP[bucket]
+             : kDefaultVariant[bucket];
 }
 
 // multi-wave global-scratch kernels: the FP64, FP32 and relativistic modes
