@@ -135,34 +135,15 @@ __global__ void k_rebin_lists(int64_t n, const int32_t *gnew, const uint32_t *fl
 }
 
 // each group's arrivals into ascending position: up to 8 in registers
-// (Batcher's odd-even merge network, 19 compare-exchanges), up to 32 by a
-// bitonic network in registers, longer lists by insertion sort in place
+// (Batcher's odd-even merge network, 19 compare-exchanges), longer lists by a
+// wave each (k_rebin_sort_long)
 __device__ __forceinline__ void cx(int32_t &a, int32_t &b) {
   const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
   a = lo;
   b = hi;
 }
-template <int N>
-__device__ __forceinline__ void bitonic(int32_t (&v)[N]) {
-#pragma unroll
-  for (int k = 2; k <= N; k <<= 1)
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1)
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const int l = i ^ j;
-        if (l > i) {
-          if ((i & k) == 0)
-            cx(v[i], v[l]);
-          else
-            cx(v[l], v[i]);
-        }
-      }
-}
-// Two kernels: the lists of at most 8 (nearly all of them when a few per cent
-// of the particles move) and the longer ones.  One kernel with both paths
-// kept the 32-entry network's registers for every thread, and its few
-// long lists held whole waves.
+// Lists of 2 to 8 entries (nearly all of them when a few per cent of the
+// particles move): one thread each.
 __global__ void k_rebin_sort(int64_t m, const int64_t *aoff, int32_t *alist) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
        g += (int64_t)gridDim.x * blockDim.x) {
@@ -193,30 +174,59 @@ __global__ void k_rebin_sort(int64_t m, const int64_t *aoff, int32_t *alist) {
     }
   }
 }
-__global__ void k_rebin_sort_long(int64_t m, const int64_t *aoff, int32_t *alist) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    int32_t *a = alist + aoff[g];
-    const int64_t k = aoff[g + 1] - aoff[g];
+// Lists longer than 8: one wave per list, sorted by the ascending bitonic
+// network on the list padded to a power of two P (stage s: each element of a
+// block of s against its mirror in the block, then half-cleaners at s/4,
+// s/8, ..., 1; every compare-exchange leaves the smaller value at the lower
+// index, so padding entries, taken as +infinity, never move and pairs that
+// reach past the list are skipped).  Lists up to LONG_LDS entries are sorted
+// in LDS, longer ones in place.  An insertion sort by one thread, as before,
+// took O(k^2) dependent loads for the few lists of some tens of arrivals that
+// a push leaves in the largest cells, and held the whole kernel on them.
+constexpr int LONG_TPB = 64, LONG_LDS = 4096;
+__global__ void __launch_bounds__(LONG_TPB)
+    k_rebin_sort_long(int64_t m, const int64_t *aoff, int32_t *alist) {
+  __shared__ int32_t buf[LONG_LDS];
+  const int lane = threadIdx.x;
+  for (int64_t g = blockIdx.x; g < m; g += gridDim.x) {
+    const int64_t k = aoff[g + 1] - aoff[g];  // (the same in every lane)
     if (k <= 8) continue;
-    if (k <= 32) {
-      int32_t v[32];
-#pragma unroll
-      for (int i = 0; i < 32; ++i) v[i] = i < k ? a[i] : INT32_MAX;
-      bitonic<32>(v);
-#pragma unroll
-      for (int i = 0; i < 32; ++i)
-        if (i < k) a[i] = v[i];
-      continue;
+    int32_t *a = alist + aoff[g];
+    const bool in_lds = k <= LONG_LDS;
+    int32_t *d = in_lds ? buf : a;
+    if (in_lds) {
+      for (int64_t i = lane; i < k; i += LONG_TPB) buf[i] = a[i];
+      __syncthreads();
     }
-    for (int64_t i = 1; i < k; ++i) {
-      const int32_t x = a[i];
-      int64_t j = i - 1;
-      while (j >= 0 && a[j] > x) {
-        a[j + 1] = a[j];
-        --j;
+    int64_t P = 1;
+    while (P < k) P <<= 1;
+    for (int64_t sz = 2; sz <= P; sz <<= 1) {
+      for (int64_t j = sz >> 1; j > 0; j >>= 1) {
+        for (int64_t x = lane; x < (P >> 1); x += LONG_TPB) {
+          int64_t i, l;
+          if (j == (sz >> 1)) {  // mirror within the block of sz
+            const int64_t blk = x / j, r = x - blk * j;
+            i = blk * sz + r;
+            l = blk * sz + sz - 1 - r;
+          } else {  // half-cleaner of stride j
+            const int64_t blk = x / j, r = x - blk * j;
+            i = blk * 2 * j + r;
+            l = i + j;
+          }
+          if (l < k) {
+            const int32_t u = d[i], v = d[l];
+            if (v < u) {
+              d[i] = v;
+              d[l] = u;
+            }
+          }
+        }
+        __syncthreads();
       }
-      a[j + 1] = x;
+    }
+    if (in_lds) {
+      for (int64_t i = lane; i < k; i += LONG_TPB) a[i] = buf[i];
+      __syncthreads();  // (before the next list reuses buf)
     }
   }
 }
@@ -311,7 +321,8 @@ hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const 
     hipLaunchKernelGGL(k_rebin_lists, dim3(grid_of(n)), dim3(256), 0, s, n, gnew, flag, aoff,
                        acur, alist);
     hipLaunchKernelGGL(k_rebin_sort, dim3(grid_of(m)), dim3(256), 0, s, m, aoff, alist);
-    hipLaunchKernelGGL(k_rebin_sort_long, dim3(grid_of(m)), dim3(256), 0, s, m, aoff, alist);
+    hipLaunchKernelGGL(k_rebin_sort_long, dim3((unsigned)(m < 4096 ? (m > 0 ? m : 1) : 4096)),
+                       dim3(LONG_TPB), 0, s, m, aoff, alist);
     hipLaunchKernelGGL(k_rebin_groups, dim3(grid_of(m)), dim3(256), 0, s, m, n, off, mpre, aoff,
                        leave, off_new, reinterpret_cast<GroupRec *>(rec));
     hipLaunchKernelGGL(k_rebin_place, dim3(grid_of(n)), dim3(256), 0, s, n, gold, gnew, mpre,

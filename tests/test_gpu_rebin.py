@@ -106,10 +106,14 @@ def test_rebin_edge_cases(ctx):
     new[cell == 0] = 5
     new[cell == 5] = 1
     _check(ctx, off, sp, new.astype(np.int32), 8, 3)
-    # many arrivals into one group
+    # many arrivals into one group (about 2500 per species: the sort of long
+    # arrival lists in LDS), and about 12000 (the same sort in place)
     off, cell, sp = _population(rng, 50, 2, 100, empty_frac=0.0)
     new = np.where(rng.uniform(size=cell.size) < 0.5, 7, cell).astype(np.int32)
     _check(ctx, off, sp, new, 50, 2)
+    off, cell, sp = _population(rng, 240, 2, 100, empty_frac=0.0)
+    new = np.where(rng.uniform(size=cell.size) < 0.5, 11, cell).astype(np.int32)
+    _check(ctx, off, sp, new, 240, 2)
     # no particles
     off = np.zeros(2 * 4 + 1, dtype=np.int64)
     _check(ctx, off, np.zeros(0, np.int32), np.zeros(0, np.int32), 4, 2)
