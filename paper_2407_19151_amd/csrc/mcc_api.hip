@@ -53,12 +53,10 @@ hipError_t launch_sample_angles(int method, int precision, int64_t n, const doub
                                 const uint32_t *a0, const uint32_t *a1, double *oc, double *st,
                                 double *A, const double2 *tab, hipStream_t st_);
 hipError_t launch_n97_table(double2 *tab, hipStream_t s);
+size_t rebin_scratch_bytes(int64_t n, int64_t m);
 hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
                         const int32_t *cells_new, int64_t *off_new, int32_t *perm,
-                        int32_t *gold, int32_t *gnew, int32_t *alist, uint32_t *flag,
-                        int64_t *mpre, uint32_t *leave, uint32_t *arrive, uint32_t *acur,
-                        uint32_t *cnt, int64_t *aoff, void *rec, int64_t *tiles, int32_t *err,
-                        hipStream_t s);
+                        void *scratch, int64_t *tiles, int32_t *err, hipStream_t s);
 hipError_t launch_gather(int64_t n, const int32_t *perm, const double *w, const double *vx,
                          const double *vy, const double *vz, double *gw, double *gx, double *gy,
                          double *gz, hipStream_t s);
@@ -155,8 +153,7 @@ struct mcc_ctx {
   // and above), per-cell lnL adjoints
   DevBuf adj_small, adj_big, adj_part;
   // incremental re-binning
-  DevBuf rb_gold, rb_gnew, rb_alist, rb_flag, rb_mpre, rb_leave, rb_arrive, rb_acur, rb_cnt,
-      rb_aoff, rb_rec;
+  DevBuf rb;
   int grid[NMODE][NVARIANT] = {};
   int variant[NBUCKET] = {};
 };
@@ -525,9 +522,7 @@ void mcc_destroy(mcc_ctx *ctx) {
   for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->tiles, &ctx->off, &ctx->perm,
                     &ctx->bin_k0, &ctx->bin_k1, &ctx->bin_v0, &ctx->bin_v1, &ctx->bin_hist,
                     &ctx->bin_pos, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97,
-                    &ctx->work, &ctx->rb_gold, &ctx->rb_gnew, &ctx->rb_alist, &ctx->rb_flag,
-                    &ctx->rb_mpre, &ctx->rb_leave, &ctx->rb_arrive, &ctx->rb_acur,
-                    &ctx->rb_cnt, &ctx->rb_aoff, &ctx->rb_rec, &ctx->adj_small, &ctx->adj_big,
+                    &ctx->work, &ctx->rb, &ctx->adj_small, &ctx->adj_big,
                     &ctx->adj_part})
     b->release();
   if (ctx->err) (void)hipFree(ctx->err);
@@ -819,15 +814,7 @@ mcc_status rebin_keys(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_specie
   if (n > (int64_t)INT32_MAX || m > (int64_t)INT32_MAX) return MCC_ERR_UNSUPPORTED;
   if (m == 0 && n > 0) return MCC_ERR_INVALID;
   HIP_TRY(hipSetDevice(ctx->device));
-  const size_t nn = (size_t)std::max<int64_t>(n, 1), mm = (size_t)std::max<int64_t>(m, 1);
-  if (!ctx->rb_gold.ensure(sizeof(int32_t) * nn) || !ctx->rb_gnew.ensure(sizeof(int32_t) * nn) ||
-      !ctx->rb_alist.ensure(sizeof(int32_t) * nn) || !ctx->rb_flag.ensure(sizeof(uint32_t) * nn) ||
-      !ctx->rb_mpre.ensure(sizeof(int64_t) * (nn + 1)) ||
-      !ctx->rb_leave.ensure(sizeof(uint32_t) * mm) ||
-      !ctx->rb_arrive.ensure(sizeof(uint32_t) * mm) ||
-      !ctx->rb_acur.ensure(sizeof(uint32_t) * mm) || !ctx->rb_cnt.ensure(sizeof(uint32_t) * mm) ||
-      !ctx->rb_aoff.ensure(sizeof(int64_t) * (mm + 1)) ||
-      !ctx->rb_rec.ensure(48 * mm) ||
+  if (!ctx->rb.ensure(rebin_scratch_bytes(n, m)) ||
       !ctx->tiles.ensure(sizeof(int64_t) * (size_t)scan_tiles_needed(std::max<int64_t>(n, m))))
     return MCC_ERR_OOM;
   if (m == 0) {
@@ -835,12 +822,7 @@ mcc_status rebin_keys(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_specie
     return MCC_OK;
   }
   HIP_TRY(launch_rebin(n, m, n_species, n_cells, offsets, cells_new, offsets_out, perm_out,
-                       ctx->rb_gold.as<int32_t>(), ctx->rb_gnew.as<int32_t>(),
-                       ctx->rb_alist.as<int32_t>(), ctx->rb_flag.as<uint32_t>(),
-                       ctx->rb_mpre.as<int64_t>(), ctx->rb_leave.as<uint32_t>(),
-                       ctx->rb_arrive.as<uint32_t>(), ctx->rb_acur.as<uint32_t>(),
-                       ctx->rb_cnt.as<uint32_t>(), ctx->rb_aoff.as<int64_t>(), ctx->rb_rec.p,
-                       ctx->tiles.as<int64_t>(), ctx->err, ctx->stream));
+                       ctx->rb.p, ctx->tiles.as<int64_t>(), ctx->err, ctx->stream));
   return MCC_OK;
 }
 }  // namespace

@@ -3,14 +3,24 @@
 // particle push).  The result is the stable grouping by the new
 // (cell, species) keys: ascending current position inside every new group,
 // the same as binning from scratch.  Most particles keep their group, so
-// the work is a few streaming passes over the particles plus the sorted
+// the work is two streaming passes over the particles plus the sorted
 // arrival list of each group:
 //   - a stayer's rank in its group is its rank among the group's stayers
-//     (its old in-group rank less the movers before it: a prefix count of
-//     the mover flags) plus the arrivals with a smaller position;
+//     (its old in-group rank less the movers before it in the group) plus
+//     the arrivals with a smaller position;
 //   - an arrival's rank is the stayers of its new group with a smaller
 //     position (the group's old segment lies wholly before or after it)
 //     plus its rank in the group's sorted arrival list.
+// Arrivals never come from inside a group's old segment, so all stayers of
+// a group have the same number of arrivals before them: the arrival lists
+// are needed only to place the arrivals themselves.
+// Positions are taken in chunks of RB_CH.  A chunk's workgroup finds the
+// group of each of its positions from the group starts inside the chunk
+// (marked in LDS, then carried forward by a max-scan), and counts the movers
+// before a position as the movers of the earlier chunks (one scan over the
+// per-chunk counts) plus those before it in the chunk (a scan inside the
+// workgroup).  Nothing per particle is kept between the passes but the
+// movers themselves.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -20,32 +30,7 @@ namespace mcc {
 
 namespace {
 
-// the group whose segment holds grouped position p (offsets[g] <= p <
-// offsets[g + 1]); with empty groups, the last g with offsets[g] <= p
-__device__ __forceinline__ int64_t group_of(const int64_t *off, int64_t m, int64_t p) {
-  int64_t lo = 0, hi = m;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (off[mid] <= p)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// number of entries of the sorted list a[0, k) below x
-__device__ __forceinline__ int64_t count_below(const int32_t *a, int64_t k, int32_t x) {
-  int64_t lo = 0, hi = k;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (a[mid] < x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
+constexpr int RB_TPB = 256, RB_PPT = 8, RB_CH = RB_TPB * RB_PPT, RB_NW = RB_TPB / 64;
 
 __global__ void k_rebin_check(const int64_t *off, int64_t m, int64_t n, int32_t *err) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
@@ -56,62 +41,199 @@ __global__ void k_rebin_check(const int64_t *off, int64_t m, int64_t n, int32_t 
   }
 }
 
-// old and new group of every position, the mover flags, and the per-group
-// counts of leavers and arrivals.  A cell id out of range is reported and
-// the particle kept where it is.  A block takes a chunk of MARK_CHUNK
-// positions: one search in HBM finds the chunk's first group, the next
-// MARK_WIN offsets go to LDS, and each position's group is searched there
-// (in HBM only when the chunk runs past the window, as across a long run of
-// empty groups).
-constexpr int MARK_TPB = 256, MARK_CHUNK = 2048, MARK_WIN = 2048;
-__global__ void __launch_bounds__(MARK_TPB)
-    k_rebin_mark(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
-                 const int32_t *cells_new, int32_t *gold, int32_t *gnew, uint32_t *flag,
-                 uint32_t *leave, uint32_t *arrive, int32_t *err) {
-  __shared__ int64_t win[MARK_WIN + 1];
-  __shared__ int64_t s_g0;
-  for (int64_t c0 = (int64_t)blockIdx.x * MARK_CHUNK; c0 < n;
-       c0 += (int64_t)gridDim.x * MARK_CHUNK) {
-    if (threadIdx.x == 0) s_g0 = group_of(off, m, c0);
-    __syncthreads();
-    const int64_t g0 = s_g0;
-    const int nw = (int)(m + 1 - g0 < MARK_WIN + 1 ? m + 1 - g0 : MARK_WIN + 1);
-    for (int i = threadIdx.x; i < nw; i += MARK_TPB) win[i] = off[g0 + i];
-    __syncthreads();
-    const int64_t c1 = c0 + MARK_CHUNK < n ? c0 + MARK_CHUNK : n;
-    for (int64_t p = c0 + threadIdx.x; p < c1; p += MARK_TPB) {
-      int64_t g;
-      if (win[nw - 1] <= p) {
-        g = group_of(off, m, p);  // past the window (win[nw - 1] = n when it reaches the end)
-      } else {
-        int lo = 0, hi = nw - 1;  // win[lo] <= p < win[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (win[mid] <= p)
-            lo = mid;
-          else
-            hi = mid;
-        }
-        g = g0 + lo;
-      }
-      const int32_t s = (int32_t)(g % S);
-      int32_t c = cells_new[p];
-      if (c < 0 || c >= n_cells) {
-        atomicCAS(err, 0, 3);
-        c = (int32_t)(g / S);
-      }
-      const int64_t g2 = (int64_t)c * S + s;
-      gold[p] = (int32_t)g;
-      gnew[p] = (int32_t)g2;
-      const bool mv = g2 != g;
-      flag[p] = mv ? 1u : 0u;
-      if (mv) {
-        atomicAdd(&leave[g], 1u);
-        atomicAdd(&arrive[g2], 1u);
-      }
+// per-group counters to zero, chunk starts to group 0 (what a chunk keeps if
+// inconsistent offsets leave it unclaimed)
+__global__ void k_rebin_zero(int64_t m, int64_t nch, uint32_t *leave, uint32_t *arrive,
+                             uint32_t *acur, uint32_t *gstart, int32_t *chunk_g0) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m || g < nch;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    if (g < m) {
+      leave[g] = 0u;
+      arrive[g] = 0u;
+      acur[g] = 0u;
+      gstart[g] = 0u;
     }
-    __syncthreads();
+    if (g < nch) chunk_g0[g] = 0;
   }
+}
+
+// the group holding the first position of every chunk: a non-empty group
+// claims the chunks whose first position lies in its segment
+__global__ void k_rebin_chunk_starts(int64_t m, int64_t n, const int64_t *off, int64_t nch,
+                                     int32_t *chunk_g0) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t o0 = off[g], o1 = off[g + 1];
+    if (!(o0 >= 0 && o1 > o0 && o1 <= n)) continue;
+    for (int64_t c = (o0 + RB_CH - 1) / RB_CH; c < nch && c * RB_CH < o1; ++c)
+      chunk_g0[c] = (int32_t)g;
+  }
+}
+
+struct ChunkLds {
+  int32_t gs[RB_CH];  // group starting at each position of the chunk (-1: none)
+  int32_t wmax[RB_NW];
+  uint32_t wsum[RB_NW];
+};
+
+__device__ __forceinline__ int32_t wave_incl_max(int32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t y = __shfl_up(x, d);
+    if (lane >= d) x = x > y ? x : y;
+  }
+  return x;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// exclusive sum over the workgroup's threads in thread order; total to all
+__device__ __forceinline__ uint32_t block_excl_sum(uint32_t x, ChunkLds &L, uint32_t &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t incl = wave_incl_sum(x);
+  if (lane == 63) L.wsum[w] = incl;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < RB_NW; ++k) {
+    const uint32_t v = L.wsum[k];
+    if (k < w) before += v;
+    tot += v;
+  }
+  total = tot;
+  return before + incl - x;
+}
+
+// The group of each of the thread's positions c0 + RB_PPT*t + j (j < RB_PPT)
+// of chunk [c0, c1), and which of them starts a non-empty group.  g0 is the
+// group holding c0.  Groups stay in [0, m) whatever the offsets hold.
+__device__ __forceinline__ void chunk_groups(int64_t c0, int64_t c1, int64_t m, int64_t n,
+                                             const int64_t *off, int32_t g0, ChunkLds &L,
+                                             int32_t (&g)[RB_PPT], uint32_t &starts) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j) L.gs[RB_PPT * t + j] = -1;
+  __syncthreads();
+  // a group that starts inside the chunk marks its first position; the
+  // batches go on while the last group of a batch still starts before c1
+  for (int64_t gb = (int64_t)g0 + 1;; gb += RB_TPB) {
+    const int64_t gg = gb + t;
+    int64_t o = n;
+    if (gg < m) {
+      o = off[gg];
+      if (o >= c0 && o < c1 && off[gg + 1] > o) L.gs[o - c0] = (int32_t)gg;
+    }
+    if (!__syncthreads_or(t == RB_TPB - 1 && gg < m && o < c1)) break;
+  }
+  int32_t v[RB_PPT];
+  int32_t mx = -1;
+  starts = 0u;
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j) {
+    v[j] = L.gs[RB_PPT * t + j];
+    if (v[j] >= 0) starts |= 1u << j;
+    mx = v[j] > mx ? v[j] : mx;
+  }
+  if (t == 0) {
+    // the chunk's first position belongs to g0; it starts g0 only if g0's
+    // segment begins there
+    v[0] = g0;
+    starts = (starts & ~1u) | (off[g0] == c0 ? 1u : 0u);
+    mx = mx > g0 ? mx : g0;
+  }
+  // carry: the largest group starting at an earlier position (groups start
+  // in ascending order)
+  const int32_t incl = wave_incl_max(mx);
+  if (lane == 63) L.wmax[w] = incl;
+  __syncthreads();
+  int32_t carry = __shfl_up(incl, 1);
+  if (lane == 0) carry = -1;
+#pragma unroll
+  for (int k = 0; k < RB_NW; ++k)
+    if (k < w) carry = L.wmax[k] > carry ? L.wmax[k] : carry;
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j) {
+    carry = v[j] > carry ? v[j] : carry;
+    g[j] = carry < 0 ? 0 : (carry >= m ? (int32_t)(m - 1) : carry);
+  }
+}
+
+// the new group of the particle at p (group g); a cell id out of range is
+// reported and the particle kept where it is
+__device__ __forceinline__ int32_t new_group(int32_t g, int32_t c, int32_t S, int32_t n_cells,
+                                             int32_t *err) {
+  const int32_t s = g % S;
+  if (c < 0 || c >= n_cells) {
+    atomicCAS(err, 0, 3);
+    return g;
+  }
+  return c * S + s;
+}
+
+__device__ __forceinline__ void load_cells(const int32_t *cells_new, int64_t p0, int64_t c1,
+                                           int32_t (&c)[RB_PPT]) {
+  // (vector loads when the array is 16-byte aligned; p0 is a multiple of 8)
+  if (p0 + RB_PPT <= c1 && ((uintptr_t)cells_new & 15) == 0) {
+    const int4 a = *reinterpret_cast<const int4 *>(cells_new + p0);
+    const int4 b = *reinterpret_cast<const int4 *>(cells_new + p0 + 4);
+    c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
+    c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < RB_PPT; ++j) c[j] = p0 + j < c1 ? cells_new[p0 + j] : 0;
+  }
+}
+
+// Pass 1, one workgroup per chunk: the movers of the chunk in position order
+// into its slice of the mover queue (position, new group), the per-group
+// counts of leavers and arrivals, the chunk's mover count, and for each
+// group that starts in the chunk the chunk's movers before its start.
+__global__ void __launch_bounds__(RB_TPB)
+    k_rebin_mark(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
+                 const int32_t *cells_new, const int32_t *chunk_g0, int32_t *mq_p,
+                 int32_t *mq_g, uint32_t *chunk_cnt, uint32_t *gstart, uint32_t *leave,
+                 uint32_t *arrive, int32_t *err) {
+  __shared__ ChunkLds L;
+  const int64_t c = blockIdx.x, c0 = c * RB_CH, c1 = c0 + RB_CH < n ? c0 + RB_CH : n;
+  const int64_t p0 = c0 + (int64_t)RB_PPT * threadIdx.x;
+  int32_t cn[RB_PPT], g2[RB_PPT];
+  load_cells(cells_new, p0, c1, cn);
+  int32_t g0 = chunk_g0[c];
+  g0 = g0 < 0 ? 0 : (g0 >= m ? (int32_t)(m - 1) : g0);
+  int32_t g[RB_PPT];
+  uint32_t starts;
+  chunk_groups(c0, c1, m, n, off, g0, L, g, starts);
+  uint32_t mv = 0u;
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j) {
+    if (p0 + j >= c1) continue;
+    g2[j] = new_group(g[j], cn[j], S, n_cells, err);
+    if (g2[j] != g[j]) mv |= 1u << j;
+  }
+  uint32_t total;
+  const uint32_t base = block_excl_sum((uint32_t)__popc(mv), L, total);
+  uint32_t r = base;
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j) {
+    if (starts & (1u << j)) gstart[g[j]] = r;
+    if (mv & (1u << j)) {
+      atomicAdd(&leave[g[j]], 1u);
+      atomicAdd(&arrive[g2[j]], 1u);
+      mq_p[c0 + r] = (int32_t)(p0 + j);
+      mq_g[c0 + r] = g2[j];
+      ++r;
+    }
+  }
+  if (threadIdx.x == 0) chunk_cnt[c] = total;
 }
 
 __global__ void k_rebin_counts(int64_t m, const int64_t *off, const uint32_t *leave,
@@ -121,164 +243,269 @@ __global__ void k_rebin_counts(int64_t m, const int64_t *off, const uint32_t *le
     cnt[g] = (uint32_t)(off[g + 1] - off[g]) - leave[g] + arrive[g];
 }
 
-// movers into their new group's arrival list (unordered: atomic slots)
-__global__ void k_rebin_lists(int64_t n, const int32_t *gnew, const uint32_t *flag,
-                              const int64_t *aoff, uint32_t *acur, int32_t *alist) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    if (!flag[p]) continue;
-    const int32_t g2 = gnew[p];
+// the movers of each chunk into their new group's arrival list (unordered:
+// atomic slots)
+__global__ void k_rebin_lists(const uint32_t *chunk_cnt, const int32_t *mq_p,
+                              const int32_t *mq_g, const int64_t *aoff, uint32_t *acur,
+                              int32_t *alist) {
+  const int64_t c0 = (int64_t)blockIdx.x * RB_CH;
+  const uint32_t k = chunk_cnt[blockIdx.x];
+  for (uint32_t i = threadIdx.x; i < k && i < (uint32_t)RB_CH; i += blockDim.x) {
+    const int32_t g2 = mq_g[c0 + i];
     const uint32_t slot = atomicAdd(&acur[g2], 1u);
     const int64_t at = aoff[g2] + slot;
-    if (at < aoff[g2 + 1]) alist[at] = (int32_t)p;
+    if (at < aoff[g2 + 1]) alist[at] = mq_p[c0 + i];
   }
 }
 
-// each group's arrivals into ascending position: up to 8 in registers
-// (Batcher's odd-even merge network, 19 compare-exchanges), longer lists by a
-// wave each (k_rebin_sort_long)
+// Per group, once the scans are done: its arrivals go to their new
+// positions and the group's stayer base is recorded.  With the group's
+// arrivals in ascending position, the one of rank i goes to
+// off_new + i + (its position before the old segment ? 0 : the stayers).
+// Arrivals never come from inside the old segment, so every stayer has the
+// same count `below` of arrivals before it, and a stayer at p goes to
+//   sbase + p - (movers before p),
+//   sbase = off_new - o0 + (movers before o0) + below.
+// A group whose offsets are inconsistent (reported by k_rebin_check) places
+// nobody: sbase = kNoGroup.
+constexpr int64_t kNoGroup = INT64_MIN;
+
+struct GroupView {
+  int64_t o0, o1, nbase, stay;
+  bool ok;
+};
+
+__device__ __forceinline__ GroupView group_view(int64_t g, int64_t n, const int64_t *off,
+                                                const int64_t *off_new, const uint32_t *leave) {
+  GroupView v;
+  const int64_t o0 = off[g], o1 = off[g + 1];
+  v.ok = o0 >= 0 && o1 >= o0 && o1 <= n;
+  v.o0 = v.ok ? o0 : 0;
+  v.o1 = v.ok ? o1 : 0;
+  v.nbase = off_new[g];
+  v.stay = v.ok ? (o1 - o0) - (int64_t)leave[g] : 0;
+  return v;
+}
+
+__device__ __forceinline__ int64_t group_sbase(const GroupView &v, int64_t g,
+                                               const int64_t *chunk_pre, const uint32_t *gstart,
+                                               int64_t below) {
+  if (!v.ok) return kNoGroup;
+  if (v.o1 <= v.o0) return 0;  // (no stayers)
+  return v.nbase - v.o0 + chunk_pre[v.o0 / RB_CH] + (int64_t)gstart[g] + below;
+}
+
+__device__ __forceinline__ void place_arrival(const GroupView &v, int64_t i, int32_t p, int64_t n,
+                                              int32_t *perm, int32_t *err) {
+  if (!v.ok) return;
+  const int64_t pos = v.nbase + i + (p < v.o0 ? 0 : v.stay);
+  if (pos < 0 || pos >= n)
+    atomicCAS(err, 0, 1);
+  else
+    perm[pos] = p;
+}
+
 __device__ __forceinline__ void cx(int32_t &a, int32_t &b) {
   const int32_t lo = a < b ? a : b, hi = a < b ? b : a;
   a = lo;
   b = hi;
 }
-// Lists of 2 to 8 entries (nearly all of them when a few per cent of the
-// particles move): one thread each.
-__global__ void k_rebin_sort(int64_t m, const int64_t *aoff, int32_t *alist) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    int32_t *a = alist + aoff[g];
-    const int64_t k = aoff[g + 1] - aoff[g];
-    if (k < 2 || k > 8) continue;
-    if (k == 2) {
-      const int32_t x = a[0], y = a[1];
-      if (y < x) {
-        a[0] = y;
-        a[1] = x;
+
+// The ascending bitonic network on N values (N a power of two): stage s
+// compares each element of a block of s with its mirror in the block, then
+// half-cleaners at s/4, s/8, ..., 1 (element i with i + j).  Every
+// compare-exchange leaves the smaller value at the lower index, so padding
+// taken as +infinity stays at the top.  Fully unrolled: the indices are
+// constants and v stays in registers.
+template <int N>
+__device__ __forceinline__ void sort_net(int32_t (&v)[N]) {
+#pragma unroll
+  for (int s = 2; s <= N; s <<= 1) {
+#pragma unroll
+    for (int j = s >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const int l = j == (s >> 1) ? (i ^ (s - 1)) : (i ^ j);
+        if (l > i) cx(v[i], v[l]);
       }
-      continue;
-    }
-    {
-      int32_t v[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) v[i] = i < k ? a[i] : INT32_MAX;
-      cx(v[0], v[1]); cx(v[2], v[3]); cx(v[4], v[5]); cx(v[6], v[7]);
-      cx(v[0], v[2]); cx(v[1], v[3]); cx(v[4], v[6]); cx(v[5], v[7]);
-      cx(v[1], v[2]); cx(v[5], v[6]);
-      cx(v[0], v[4]); cx(v[1], v[5]); cx(v[2], v[6]); cx(v[3], v[7]);
-      cx(v[2], v[4]); cx(v[3], v[5]);
-      cx(v[1], v[2]); cx(v[3], v[4]); cx(v[5], v[6]);
-#pragma unroll
-      for (int i = 0; i < 8; ++i)
-        if (i < k) a[i] = v[i];
     }
   }
 }
-// Lists longer than 8: one wave per list, sorted by the ascending bitonic
-// network on the list padded to a power of two P (stage s: each element of a
-// block of s against its mirror in the block, then half-cleaners at s/4,
-// s/8, ..., 1; every compare-exchange leaves the smaller value at the lower
-// index, so padding entries, taken as +infinity, never move and pairs that
-// reach past the list are skipped).  Lists up to LONG_LDS entries are sorted
-// in LDS, longer ones in place.  An insertion sort by one thread, as before,
-// took O(k^2) dependent loads for the few lists of some tens of arrivals that
-// a push leaves in the largest cells, and held the whole kernel on them.
-constexpr int LONG_TPB = 64, LONG_LDS = 4096;
-__global__ void __launch_bounds__(LONG_TPB)
-    k_rebin_sort_long(int64_t m, const int64_t *aoff, int32_t *alist) {
+
+// a list of at most N arrivals: sorted in registers, placed; returns how
+// many lie before the old segment
+template <int N>
+__device__ __forceinline__ int64_t place_list_regs(const int32_t *a, int64_t k,
+                                                   const GroupView &gv, int64_t n,
+                                                   int32_t *perm, int32_t *err) {
+  int32_t v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = i < k ? a[i] : INT32_MAX;
+  if (N > 1) sort_net<N>(v);
+  int64_t below = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (i < k) {
+      below += v[i] < gv.o0 ? 1 : 0;
+      place_arrival(gv, i, v[i], n, perm, err);
+    }
+  }
+  return below;
+}
+
+// Groups with at most 32 arrivals (nearly all of them when a few per cent of
+// the particles move): one thread each.
+__global__ void k_rebin_place_arrivals(int64_t m, int64_t n, const int64_t *off,
+                                       const int64_t *off_new, const uint32_t *leave,
+                                       const int64_t *aoff, const int32_t *alist,
+                                       const int64_t *chunk_pre, const uint32_t *gstart,
+                                       int64_t *sbase, int32_t *perm, int32_t *err) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a0 = aoff[g], k = aoff[g + 1] - a0;
+    if (k > 32) continue;  // (k_rebin_place_arrivals_long)
+    const GroupView gv = group_view(g, n, off, off_new, leave);
+    const int32_t *a = alist + a0;
+    int64_t below = 0;
+    if (k == 0)
+      below = 0;
+    else if (k == 1)
+      below = place_list_regs<1>(a, k, gv, n, perm, err);
+    else if (k == 2)
+      below = place_list_regs<2>(a, k, gv, n, perm, err);
+    else if (k <= 8)
+      below = place_list_regs<8>(a, k, gv, n, perm, err);
+    else if (k <= 16)
+      below = place_list_regs<16>(a, k, gv, n, perm, err);
+    else
+      below = place_list_regs<32>(a, k, gv, n, perm, err);
+    sbase[g] = group_sbase(gv, g, chunk_pre, gstart, below);
+  }
+}
+
+// Groups with more than 32 arrivals: a wave per block of 64 groups finds
+// them (one load of the block's offsets and a ballot) and takes them one
+// after the other: the same network over the wave's lanes with shuffles up
+// to 64 arrivals, in LDS up to LONG_LDS, in place in the list beyond; then
+// every arrival to its position.
+constexpr int LONG_LDS = 4096;
+__global__ void __launch_bounds__(64)
+    k_rebin_place_arrivals_long(int64_t m, int64_t n, const int64_t *off, const int64_t *off_new,
+                                const uint32_t *leave, const int64_t *aoff, int32_t *alist,
+                                const int64_t *chunk_pre, const uint32_t *gstart,
+                                int64_t *sbase, int32_t *perm, int32_t *err) {
   __shared__ int32_t buf[LONG_LDS];
   const int lane = threadIdx.x;
-  for (int64_t g = blockIdx.x; g < m; g += gridDim.x) {
-    const int64_t k = aoff[g + 1] - aoff[g];  // (the same in every lane)
-    if (k <= 8) continue;
-    int32_t *a = alist + aoff[g];
-    const bool in_lds = k <= LONG_LDS;
-    int32_t *d = in_lds ? buf : a;
-    if (in_lds) {
-      for (int64_t i = lane; i < k; i += LONG_TPB) buf[i] = a[i];
-      __syncthreads();
-    }
-    int64_t P = 1;
-    while (P < k) P <<= 1;
-    for (int64_t sz = 2; sz <= P; sz <<= 1) {
-      for (int64_t j = sz >> 1; j > 0; j >>= 1) {
-        for (int64_t x = lane; x < (P >> 1); x += LONG_TPB) {
-          int64_t i, l;
-          if (j == (sz >> 1)) {  // mirror within the block of sz
-            const int64_t blk = x / j, r = x - blk * j;
-            i = blk * sz + r;
-            l = blk * sz + sz - 1 - r;
-          } else {  // half-cleaner of stride j
-            const int64_t blk = x / j, r = x - blk * j;
-            i = blk * 2 * j + r;
-            l = i + j;
-          }
-          if (l < k) {
-            const int32_t u = d[i], v = d[l];
-            if (v < u) {
-              d[i] = v;
-              d[l] = u;
-            }
+  for (int64_t gb = (int64_t)blockIdx.x * 64; gb < m; gb += (int64_t)gridDim.x * 64) {
+    const int64_t gl = gb + lane;
+    const int64_t a0l = gl < m ? aoff[gl] : 0, kl = gl < m ? aoff[gl + 1] - a0l : 0;
+    uint64_t todo = __ballot(kl > 32);
+    while (todo) {
+      const int b = __ffsll((unsigned long long)todo) - 1;
+      todo &= todo - 1;
+      const int64_t g = gb + b;
+      const int64_t a0 = __shfl(a0l, b), k = __shfl(kl, b);
+      const GroupView gv = group_view(g, n, off, off_new, leave);
+      int32_t *a = alist + a0;
+      uint32_t below = 0;
+      if (k <= 64) {
+        int32_t v = lane < k ? a[lane] : INT32_MAX;
+#pragma unroll
+        for (int s = 2; s <= 64; s <<= 1) {
+#pragma unroll
+          for (int j = s >> 1; j > 0; j >>= 1) {
+            const int l = j == (s >> 1) ? (lane ^ (s - 1)) : (lane ^ j);
+            const int32_t u = __shfl(v, l);
+            v = (lane < l) == (u > v) ? v : u;  // lower index keeps the smaller
           }
         }
-        __syncthreads();
+        if (lane < k) place_arrival(gv, lane, v, n, perm, err);
+        below = (uint32_t)__popcll(__ballot(lane < k && v < gv.o0));
+      } else {
+        const bool in_lds = k <= LONG_LDS;
+        int32_t *d = in_lds ? buf : a;
+        if (in_lds) {
+          for (int64_t i = lane; i < k; i += 64) buf[i] = a[i];
+          __syncthreads();
+        }
+        int64_t P = 1;
+        while (P < k) P <<= 1;
+        for (int64_t sz = 2; sz <= P; sz <<= 1) {
+          for (int64_t j = sz >> 1; j > 0; j >>= 1) {
+            for (int64_t x = lane; x < (P >> 1); x += 64) {
+              const int64_t blk = x / j, r = x - blk * j;
+              int64_t i, l;
+              if (j == (sz >> 1)) {  // mirror within the block of sz
+                i = blk * sz + r;
+                l = blk * sz + sz - 1 - r;
+              } else {  // half-cleaner of stride j
+                i = blk * 2 * j + r;
+                l = i + j;
+              }
+              if (l < k) {
+                const int32_t u = d[i], w = d[l];
+                if (w < u) {
+                  d[i] = w;
+                  d[l] = u;
+                }
+              }
+            }
+            __syncthreads();
+          }
+        }
+        for (int64_t i0 = 0; i0 < k; i0 += 64) {
+          const int64_t i = i0 + lane;
+          const int32_t p = i < k ? d[i] : INT32_MAX;
+          if (i < k) place_arrival(gv, i, p, n, perm, err);
+          below += (uint32_t)__popcll(__ballot(i < k && p < gv.o0));
+        }
+        __syncthreads();  // (before the next list reuses buf)
       }
-    }
-    if (in_lds) {
-      for (int64_t i = lane; i < k; i += LONG_TPB) a[i] = buf[i];
-      __syncthreads();  // (before the next list reuses buf)
+      if (lane == 0) sbase[g] = group_sbase(gv, g, chunk_pre, gstart, below);
     }
   }
 }
 
-// Per group, once the scans are done, everything a particle of it needs:
-//   sbase  new position of a stayer at p is sbase + p - mpre[p] + (arrivals
-//          below p): off_new - off + (movers before the old segment)
-//   nbase  new offset; o0 old segment start; stay its stayers (for arrivals)
-//   a0, k  the group's sorted arrival list
-struct GroupRec {
-  int64_t sbase, nbase, o0, a0;
-  int32_t stay, k, ok, pad;
-};
-static_assert(sizeof(GroupRec) == 48, "the API allocates 48 bytes per group");
-__global__ void k_rebin_groups(int64_t m, int64_t n, const int64_t *off, const int64_t *mpre,
-                               const int64_t *aoff, const uint32_t *leave,
-                               const int64_t *off_new, GroupRec *rec) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t o0 = off[g], o1 = off[g + 1];
-    GroupRec r;
-    r.ok = (o0 >= 0 && o1 >= o0 && o1 <= n) ? 1 : 0;  // inconsistent offsets (reported)
-    const int64_t c0 = r.ok ? o0 : 0;
-    r.sbase = off_new[g] - c0 + mpre[c0];
-    r.nbase = off_new[g];
-    r.o0 = c0;
-    r.stay = r.ok ? (int32_t)((o1 - o0) - (int64_t)leave[g]) : 0;
-    r.a0 = aoff[g];
-    r.k = (int32_t)(aoff[g + 1] - aoff[g]);
-    r.pad = 0;
-    rec[g] = r;
+// Pass 2, one workgroup per chunk: every stayer to its new position.
+__global__ void __launch_bounds__(RB_TPB)
+    k_rebin_place(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
+                  const int32_t *cells_new, const int32_t *chunk_g0, const int64_t *chunk_pre,
+                  const int64_t *sbase, int32_t *perm, int32_t *err) {
+  __shared__ ChunkLds L;
+  const int64_t c = blockIdx.x, c0 = c * RB_CH, c1 = c0 + RB_CH < n ? c0 + RB_CH : n;
+  const int64_t p0 = c0 + (int64_t)RB_PPT * threadIdx.x;
+  int32_t cn[RB_PPT];
+  load_cells(cells_new, p0, c1, cn);
+  int32_t g0 = chunk_g0[c];
+  g0 = g0 < 0 ? 0 : (g0 >= m ? (int32_t)(m - 1) : g0);
+  int32_t g[RB_PPT];
+  uint32_t starts;
+  chunk_groups(c0, c1, m, n, off, g0, L, g, starts);
+  uint32_t mv = 0u;
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j) {
+    if (p0 + j >= c1) continue;
+    // (a cell id out of range was reported by the first pass: the particle stays)
+    const int32_t g2 = (cn[j] < 0 || cn[j] >= n_cells) ? g[j] : cn[j] * S + g[j] % S;
+    if (g2 != g[j]) mv |= 1u << j;
   }
-}
-
-__global__ void k_rebin_place(int64_t n, const int32_t *gold, const int32_t *gnew,
-                              const int64_t *mpre, const GroupRec *rec, const int32_t *alist,
-                              int32_t *perm, int32_t *err) {
-  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t go = gold[p], gn = gnew[p];
-    const bool stayer = go == gn;
-    const int64_t mp = stayer ? mpre[p] : 0;
-    const GroupRec r = rec[gn];
-    if (!r.ok) continue;
-    const int64_t below = r.k ? count_below(alist + r.a0, r.k, (int32_t)p) : 0;
-    const int64_t pos = stayer ? r.sbase + p - mp + below
-                               : r.nbase + (p < r.o0 ? 0 : (int64_t)r.stay) + below;
-    if (pos < 0 || pos >= n) {
-      atomicCAS(err, 0, 1);
+  uint32_t total;
+  int64_t before = chunk_pre[c] + block_excl_sum((uint32_t)__popc(mv), L, total);
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j) {
+    const int64_t p = p0 + j;
+    if (p >= c1) continue;
+    if (mv & (1u << j)) {
+      ++before;
       continue;
     }
-    perm[pos] = (int32_t)p;
+    const int64_t sb = sbase[g[j]];
+    if (sb == kNoGroup) continue;
+    const int64_t pos = sb + p - before;
+    if (pos < 0 || pos >= n)
+      atomicCAS(err, 0, 1);
+    else
+      perm[pos] = (int32_t)p;
   }
 }
 
@@ -287,46 +514,77 @@ inline int grid_of(int64_t n) {
   return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
 }
 
+inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 }  // namespace
 
-hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
 hipError_t launch_scan(const uint32_t *counts, int64_t m, int64_t *tiles, int64_t *offsets,
                        hipStream_t s);
 
-// scratch: gold, gnew, alist int32[n]; flag uint32[n]; mpre int64[n + 1];
-// leave, arrive, acur, cnt uint32[m]; aoff int64[m + 1]; rec GroupRec[m];
-// tiles of the scans
+// scratch of launch_rebin: the mover queue (position, new group) and the
+// arrival lists, int32[n] each; per chunk of 2048 positions its first
+// group, mover count and the scan of the counts; per group the leaver,
+// arrival, slot and start counters, the arrival offsets and the stayer base
+size_t rebin_scratch_bytes(int64_t n, int64_t m) {
+  const size_t nn = (size_t)(n > 0 ? n : 1), mm = (size_t)(m > 0 ? m : 1);
+  const size_t nch = (nn + RB_CH - 1) / RB_CH;
+  return 3 * align256(4 * nn) + 2 * align256(4 * nch) + align256(8 * (nch + 1)) +
+         5 * align256(4 * mm) + align256(8 * (mm + 1)) + align256(8 * mm);
+}
+
 hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
                         const int32_t *cells_new, int64_t *off_new, int32_t *perm,
-                        int32_t *gold, int32_t *gnew, int32_t *alist, uint32_t *flag,
-                        int64_t *mpre, uint32_t *leave, uint32_t *arrive, uint32_t *acur,
-                        uint32_t *cnt, int64_t *aoff, void *rec, int64_t *tiles, int32_t *err,
-                        hipStream_t s) {
+                        void *scratch, int64_t *tiles, int32_t *err, hipStream_t s) {
+  const size_t nn = (size_t)(n > 0 ? n : 1), mm = (size_t)(m > 0 ? m : 1);
+  const int64_t nch = (n + RB_CH - 1) / RB_CH;
+  const size_t nchs = (nn + RB_CH - 1) / RB_CH;
+  char *p = static_cast<char *>(scratch);
+  auto take = [&](size_t bytes) {
+    char *q = p;
+    p += align256(bytes);
+    return q;
+  };
+  int32_t *mq_p = reinterpret_cast<int32_t *>(take(4 * nn));
+  int32_t *mq_g = reinterpret_cast<int32_t *>(take(4 * nn));
+  int32_t *alist = reinterpret_cast<int32_t *>(take(4 * nn));
+  int32_t *chunk_g0 = reinterpret_cast<int32_t *>(take(4 * nchs));
+  uint32_t *chunk_cnt = reinterpret_cast<uint32_t *>(take(4 * nchs));
+  int64_t *chunk_pre = reinterpret_cast<int64_t *>(take(8 * (nchs + 1)));
+  uint32_t *leave = reinterpret_cast<uint32_t *>(take(4 * mm));
+  uint32_t *arrive = reinterpret_cast<uint32_t *>(take(4 * mm));
+  uint32_t *acur = reinterpret_cast<uint32_t *>(take(4 * mm));
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(take(4 * mm));
+  uint32_t *gstart = reinterpret_cast<uint32_t *>(take(4 * mm));
+  int64_t *aoff = reinterpret_cast<int64_t *>(take(8 * (mm + 1)));
+  int64_t *sbase = reinterpret_cast<int64_t *>(take(8 * mm));
+
   hipError_t e;
-  for (uint32_t *b : {leave, arrive, acur})
-    if ((e = launch_fill_u32(b, 0u, m, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rebin_zero, dim3(grid_of(m > nch ? m : nch)), dim3(256), 0, s, m, nch,
+                     leave, arrive, acur, gstart, chunk_g0);
   hipLaunchKernelGGL(k_rebin_check, dim3(grid_of(m)), dim3(256), 0, s, off, m, n, err);
   if (n > 0) {
-    const int64_t chunks = (n + MARK_CHUNK - 1) / MARK_CHUNK;
-    hipLaunchKernelGGL(k_rebin_mark, dim3((unsigned)(chunks < 8192 ? chunks : 8192)),
-                       dim3(MARK_TPB), 0, s, n, m, S, n_cells, off, cells_new, gold, gnew, flag,
-                       leave, arrive, err);
+    hipLaunchKernelGGL(k_rebin_chunk_starts, dim3(grid_of(m)), dim3(256), 0, s, m, n, off, nch,
+                       chunk_g0);
+    hipLaunchKernelGGL(k_rebin_mark, dim3((unsigned)nch), dim3(RB_TPB), 0, s, n, m, S, n_cells,
+                       off, cells_new, chunk_g0, mq_p, mq_g, chunk_cnt, gstart, leave, arrive,
+                       err);
   }
   hipLaunchKernelGGL(k_rebin_counts, dim3(grid_of(m)), dim3(256), 0, s, m, off, leave, arrive,
                      cnt);
   if ((e = launch_scan(cnt, m, tiles, off_new, s)) != hipSuccess) return e;
-  if ((e = launch_scan(arrive, m, tiles, aoff, s)) != hipSuccess) return e;
-  if ((e = launch_scan(flag, n, tiles, mpre, s)) != hipSuccess) return e;
   if (n > 0) {
-    hipLaunchKernelGGL(k_rebin_lists, dim3(grid_of(n)), dim3(256), 0, s, n, gnew, flag, aoff,
-                       acur, alist);
-    hipLaunchKernelGGL(k_rebin_sort, dim3(grid_of(m)), dim3(256), 0, s, m, aoff, alist);
-    hipLaunchKernelGGL(k_rebin_sort_long, dim3((unsigned)(m < 4096 ? (m > 0 ? m : 1) : 4096)),
-                       dim3(LONG_TPB), 0, s, m, aoff, alist);
-    hipLaunchKernelGGL(k_rebin_groups, dim3(grid_of(m)), dim3(256), 0, s, m, n, off, mpre, aoff,
-                       leave, off_new, reinterpret_cast<GroupRec *>(rec));
-    hipLaunchKernelGGL(k_rebin_place, dim3(grid_of(n)), dim3(256), 0, s, n, gold, gnew, mpre,
-                       reinterpret_cast<const GroupRec *>(rec), alist, perm, err);
+    if ((e = launch_scan(arrive, m, tiles, aoff, s)) != hipSuccess) return e;
+    if ((e = launch_scan(chunk_cnt, nch, tiles, chunk_pre, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rebin_lists, dim3((unsigned)nch), dim3(256), 0, s, chunk_cnt, mq_p, mq_g,
+                       aoff, acur, alist);
+    hipLaunchKernelGGL(k_rebin_place_arrivals, dim3(grid_of(m)), dim3(256), 0, s, m, n, off,
+                       off_new, leave, aoff, alist, chunk_pre, gstart, sbase, perm, err);
+    const int64_t wb = (m + 63) / 64;
+    hipLaunchKernelGGL(k_rebin_place_arrivals_long, dim3((unsigned)(wb < 8192 ? wb : 8192)),
+                       dim3(64), 0, s, m, n, off, off_new, leave, aoff, alist, chunk_pre, gstart,
+                       sbase, perm, err);
+    hipLaunchKernelGGL(k_rebin_place, dim3((unsigned)nch), dim3(RB_TPB), 0, s, n, m, S, n_cells,
+                       off, cells_new, chunk_g0, chunk_pre, sbase, perm, err);
   }
   return hipGetLastError();
 }

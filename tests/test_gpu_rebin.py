@@ -10,7 +10,9 @@ in place (mcc_rebin) and into separate output arrays (mcc_rebin_out, which
 must leave its inputs untouched).
 Cases: no movers, neighbour moves at several rates, far jumps, every
 particle moving, emptied and newly filled groups, one cell, three species,
-no particles, and cell ids out of range (reported; such particles stay).
+no particles, long arrival lists (sorted in LDS and in place), long runs of
+empty groups, a cells array that is not 16-byte aligned, and cell ids out of
+range (reported; such particles stay).
 """
 import numpy as np
 import pytest
@@ -114,6 +116,20 @@ def test_rebin_edge_cases(ctx):
     off, cell, sp = _population(rng, 240, 2, 100, empty_frac=0.0)
     new = np.where(rng.uniform(size=cell.size) < 0.5, 11, cell).astype(np.int32)
     _check(ctx, off, sp, new, 240, 2)
+    # long runs of empty groups (hundreds inside one chunk of positions, and
+    # chunks that start inside a run), some movers landing in them
+    n_cells, S = 6000, 2
+    counts = rng.poisson(30, size=(n_cells, S))
+    counts[500:2500] = 0
+    counts[3000:3400, 1] = 0
+    counts[rng.uniform(size=(n_cells, S)) < 0.3] = 0
+    flat = counts.reshape(-1)
+    off = np.zeros(flat.size + 1, dtype=np.int64)
+    np.cumsum(flat, out=off[1:])
+    cell = np.repeat(np.repeat(np.arange(n_cells, dtype=np.int32), S), flat)
+    sp = np.repeat(np.tile(np.arange(S, dtype=np.int32), n_cells), flat)
+    new = _push(rng, cell, n_cells, 0.05, far=0.5)
+    _check(ctx, off, sp, new, n_cells, S)
     # no particles
     off = np.zeros(2 * 4 + 1, dtype=np.int64)
     _check(ctx, off, np.zeros(0, np.int32), np.zeros(0, np.int32), 4, 2)
@@ -155,3 +171,21 @@ def test_rebin_full_size_population(ctx):
     cell = wl.cells.astype(np.int32)
     _check(ctx, wl.offsets, wl.species.astype(np.int32), _push(rng, cell, wl.n_cells, 0.02),
            wl.n_cells, wl.n_species)
+
+
+def test_rebin_reads_cells_at_any_alignment(ctx):
+    """cells_new one element into a larger array (4-byte aligned only)."""
+    import torch
+    rng = np.random.default_rng(13)
+    n_cells, S = 700, 2
+    off, cell, sp = _population(rng, n_cells, S, 30)
+    new = _push(rng, cell, n_cells, 0.05)
+    big = torch.from_numpy(np.concatenate([[0], new]).astype(np.int32)).cuda()
+    view = big[1:]
+    assert view.data_ptr() % 16 != 0
+    off_new, perm = ctx.rebin(torch.from_numpy(off).cuda(), view, n_cells, S)
+    torch.cuda.synchronize()
+    assert ctx.device_error() == 0
+    ref_off, ref_perm = oracle.bin_particles(new, sp, n_cells, S)
+    assert np.array_equal(off_new.cpu().numpy(), ref_off)
+    assert np.array_equal(perm.cpu().numpy().astype(np.int64), ref_perm)
