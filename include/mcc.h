@@ -364,10 +364,11 @@ mcc_status mcc_bin(mcc_ctx *ctx, int64_t n, const int32_t *cells,
  *               species of each position
  *  weights, vx, vy, vz  device double[n], all or none (NULL): permuted in
  *               place to the new order
- * Cost: streaming passes over the particles, plus sum over groups of the
- * square of the particles arriving in that group (each group's arrival list
- * is sorted in one thread): meant for partial moves; rebuild a wholesale
- * reshuffle with mcc_bin.  Data errors (cell id out of range, inconsistent
+ * Cost: two streaming passes over cells_new (the second also writes
+ * perm_out) and work on the movers only: each group's arrivals are sorted
+ * by position (a sorting network: one thread for up to 32, a wave beyond).
+ * Meant for partial moves; rebuild a wholesale reshuffle with mcc_bin.
+ * Context scratch: about 12 bytes per particle and 36 per group.  Data errors (cell id out of range, inconsistent
  * offsets) are latched as for the collide calls; such a particle keeps its
  * cell.  Errors: MCC_ERR_INVALID for bad arguments (some payload pointers
  * only), MCC_ERR_UNSUPPORTED above 2^31 - 1 particles or groups.
