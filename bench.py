@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 # v read 24, v write 24, and 8 for the cell and species ids a particle
 # carries (here implied by the offsets, whose per-group entries are < 0.1 %)
 BYTES_PER_PARTICLE_STEP = 64
+BYTES_MOVED = 56  # what the sorted kernel itself reads and writes per particle
 # the unsorted entry: the sorted step plus binning (ids in, permutation out:
 # 12 B) and the payload moved each way (w, v gathered: 32 + 32 B; v
 # scattered back: 24 + 24 B) and the permutation read twice (8 B): 150 B
@@ -769,7 +770,11 @@ def main():
                      "kernel": kname, "bucket_max_cell": BUCKET_CAP[dom],
                      "bucket_particles": per_bucket_n[dom], "launch_ms": dom_ms,
                      "algorithmic_bytes_per_launch": alg_bytes,
-                     "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP},
+                     "bytes_per_particle_step": BYTES_PER_PARTICLE_STEP,
+                     # the same on the 56 B the sorted kernel itself moves
+                     # (w in, v in and out: the ids are implied by the offsets)
+                     "frac_bytes_moved": achieved * BYTES_MOVED / BYTES_PER_PARTICLE_STEP
+                     / HBM_PEAK_GBS},
         "valu_roofline": (
             {"bound": "valu", "achieved": valu[tkey][0] / (dom_ms * 1e-3),
              "peak": VALU_PEAK_WINST, "unit": "wave-instructions/s",

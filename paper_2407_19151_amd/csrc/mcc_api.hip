@@ -54,6 +54,7 @@ hipError_t launch_sample_angles(int method, int precision, int64_t n, const doub
                                 double *A, const double2 *tab, hipStream_t st_);
 hipError_t launch_n97_table(double2 *tab, hipStream_t s);
 size_t rebin_scratch_bytes(int64_t n, int64_t m);
+int64_t rebin_tiles_needed(int64_t n, int64_t m);
 hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
                         const int32_t *cells_new, int64_t *off_new, int32_t *perm,
                         void *scratch, int64_t *tiles, int32_t *err, hipStream_t s);
@@ -815,7 +816,7 @@ mcc_status rebin_keys(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_specie
   if (m == 0 && n > 0) return MCC_ERR_INVALID;
   HIP_TRY(hipSetDevice(ctx->device));
   if (!ctx->rb.ensure(rebin_scratch_bytes(n, m)) ||
-      !ctx->tiles.ensure(sizeof(int64_t) * (size_t)scan_tiles_needed(std::max<int64_t>(n, m))))
+      !ctx->tiles.ensure(sizeof(int64_t) * (size_t)rebin_tiles_needed(n, m)))
     return MCC_ERR_OOM;
   if (m == 0) {
     HIP_TRY(launch_set_u64(reinterpret_cast<uint64_t *>(offsets_out), 0ull, ctx->stream));

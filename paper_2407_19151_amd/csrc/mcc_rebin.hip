@@ -14,7 +14,7 @@
 // Arrivals never come from inside a group's old segment, so all stayers of
 // a group have the same number of arrivals before them: the arrival lists
 // are needed only to place the arrivals themselves.
-// Positions are taken in chunks of RB_CH.  A chunk's workgroup finds the
+// Positions are taken in chunks of RB_CH (2048).  A chunk's workgroup finds the
 // group of each of its positions from the group starts inside the chunk
 // (marked in LDS, then carried forward by a max-scan), and counts the movers
 // before a position as the movers of the earlier chunks (one scan over the
@@ -32,38 +32,23 @@ namespace {
 
 constexpr int RB_TPB = 256, RB_PPT = 8, RB_CH = RB_TPB * RB_PPT, RB_NW = RB_TPB / 64;
 
-__global__ void k_rebin_check(const int64_t *off, int64_t m, int64_t n, int32_t *err) {
+// Per group, before the passes: its counters to zero, its offsets checked
+// (inconsistent ones are reported), and the chunks whose first position lies
+// in its segment claimed (their first group).  With consistent offsets every
+// chunk is claimed once; otherwise a chunk may keep an earlier value, which
+// the passes clamp into [0, m).
+__global__ void k_rebin_prep(int64_t m, int64_t n, const int64_t *off, int64_t nch,
+                             uint32_t *leave, uint32_t *arrive, uint32_t *acur, uint32_t *gstart,
+                             int32_t *chunk_g0, int32_t *err) {
   for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
        g += (int64_t)gridDim.x * blockDim.x) {
-    const bool bad = off[g + 1] < off[g] || (g == 0 && off[0] != 0) ||
-                     (g == m - 1 && off[m] != n);
-    if (bad) atomicCAS(err, 0, 1);
-  }
-}
-
-// per-group counters to zero, chunk starts to group 0 (what a chunk keeps if
-// inconsistent offsets leave it unclaimed)
-__global__ void k_rebin_zero(int64_t m, int64_t nch, uint32_t *leave, uint32_t *arrive,
-                             uint32_t *acur, uint32_t *gstart, int32_t *chunk_g0) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m || g < nch;
-       g += (int64_t)gridDim.x * blockDim.x) {
-    if (g < m) {
-      leave[g] = 0u;
-      arrive[g] = 0u;
-      acur[g] = 0u;
-      gstart[g] = 0u;
-    }
-    if (g < nch) chunk_g0[g] = 0;
-  }
-}
-
-// the group holding the first position of every chunk: a non-empty group
-// claims the chunks whose first position lies in its segment
-__global__ void k_rebin_chunk_starts(int64_t m, int64_t n, const int64_t *off, int64_t nch,
-                                     int32_t *chunk_g0) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
-       g += (int64_t)gridDim.x * blockDim.x) {
+    leave[g] = 0u;
+    arrive[g] = 0u;
+    acur[g] = 0u;
+    gstart[g] = 0u;
     const int64_t o0 = off[g], o1 = off[g + 1];
+    const bool bad = o1 < o0 || (g == 0 && o0 != 0) || (g == m - 1 && o1 != n);
+    if (bad) atomicCAS(err, 0, 1);
     if (!(o0 >= 0 && o1 > o0 && o1 <= n)) continue;
     for (int64_t c = (o0 + RB_CH - 1) / RB_CH; c < nch && c * RB_CH < o1; ++c)
       chunk_g0[c] = (int32_t)g;
@@ -181,12 +166,16 @@ __device__ __forceinline__ int32_t new_group(int32_t g, int32_t c, int32_t S, in
 
 __device__ __forceinline__ void load_cells(const int32_t *cells_new, int64_t p0, int64_t c1,
                                            int32_t (&c)[RB_PPT]) {
-  // (vector loads when the array is 16-byte aligned; p0 is a multiple of 8)
+  // (vector loads when the array is 16-byte aligned; p0 is a multiple of RB_PPT)
   if (p0 + RB_PPT <= c1 && ((uintptr_t)cells_new & 15) == 0) {
-    const int4 a = *reinterpret_cast<const int4 *>(cells_new + p0);
-    const int4 b = *reinterpret_cast<const int4 *>(cells_new + p0 + 4);
-    c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w;
-    c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+#pragma unroll
+    for (int q = 0; q < RB_PPT / 4; ++q) {
+      const int4 a = *reinterpret_cast<const int4 *>(cells_new + p0 + 4 * q);
+      c[4 * q] = a.x;
+      c[4 * q + 1] = a.y;
+      c[4 * q + 2] = a.z;
+      c[4 * q + 3] = a.w;
+    }
   } else {
 #pragma unroll
     for (int j = 0; j < RB_PPT; ++j) c[j] = p0 + j < c1 ? cells_new[p0 + j] : 0;
@@ -236,11 +225,113 @@ __global__ void __launch_bounds__(RB_TPB)
   if (threadIdx.x == 0) chunk_cnt[c] = total;
 }
 
-__global__ void k_rebin_counts(int64_t m, const int64_t *off, const uint32_t *leave,
-                               const uint32_t *arrive, uint32_t *cnt) {
-  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < m;
-       g += (int64_t)gridDim.x * blockDim.x)
-    cnt[g] = (uint32_t)(off[g + 1] - off[g]) - leave[g] + arrive[g];
+// The three exclusive scans after the first pass, in one set of launches:
+// array 0 the new group sizes (size - leavers + arrivals, computed on the
+// fly) into off_new, array 1 the arrival counts into aoff, array 2 the
+// chunks' mover counts into chunk_pre; each output gets its total at the
+// end.  Tiles of RB_CH entries; the tiles of the three arrays follow one
+// another in the grid.
+struct Scan3 {
+  const int64_t *off;
+  const uint32_t *leave, *arrive, *chunk_cnt;
+  int64_t m, nch, nt0, nt1, nt2;
+  int64_t *off_new, *aoff, *chunk_pre;
+};
+
+__device__ __forceinline__ uint32_t scan3_in(const Scan3 &S3, int a, int64_t i) {
+  if (a == 0)
+    return (uint32_t)(S3.off[i + 1] - S3.off[i]) - S3.leave[i] + S3.arrive[i];
+  return a == 1 ? S3.arrive[i] : S3.chunk_cnt[i];
+}
+
+// which array the tile b belongs to, its first entry and the array's length
+__device__ __forceinline__ int scan3_tile(const Scan3 &S3, int64_t b, int64_t &t0, int64_t &len) {
+  if (b < S3.nt0) {
+    t0 = b;
+    len = S3.m;
+    return 0;
+  }
+  if (b < S3.nt0 + S3.nt1) {
+    t0 = b - S3.nt0;
+    len = S3.m;
+    return 1;
+  }
+  t0 = b - S3.nt0 - S3.nt1;
+  len = S3.nch;
+  return 2;
+}
+
+__global__ void __launch_bounds__(RB_TPB) k_rebin_scan_tiles(Scan3 S3, int64_t *tiles) {
+  __shared__ ChunkLds L;
+  int64_t t0, len;
+  const int a = scan3_tile(S3, blockIdx.x, t0, len);
+  const int64_t base = t0 * RB_CH + (int64_t)RB_PPT * threadIdx.x;
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j)
+    if (base + j < len) sum += scan3_in(S3, a, base + j);
+  uint32_t total;
+  block_excl_sum(sum, L, total);
+  if (threadIdx.x == 0) tiles[blockIdx.x] = total;
+}
+
+// one workgroup: each array's tile sums into exclusive tile offsets
+__global__ void __launch_bounds__(RB_TPB) k_rebin_scan_sums(Scan3 S3, int64_t *tiles) {
+  __shared__ int64_t wtot[RB_NW];
+  const int t = threadIdx.x;
+  const int64_t seg0[3] = {0, S3.nt0, S3.nt0 + S3.nt1};
+  const int64_t segn[3] = {S3.nt0, S3.nt1, S3.nt2};
+  for (int a = 0; a < 3; ++a) {
+    int64_t *ts = tiles + seg0[a];
+    const int64_t nt = segn[a];
+    const int64_t per = (nt + RB_TPB - 1) / RB_TPB;
+    const int64_t lo = t * per, hi = lo + per < nt ? lo + per : nt;
+    int64_t acc = 0;
+    for (int64_t i = lo; i < hi; ++i) acc += ts[i];
+    // exclusive scan of the threads' sums: in each wave by shuffles, then
+    // across the waves
+    int64_t incl = acc;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t y = __shfl_up(incl, d);
+      if ((t & 63) >= d) incl += y;
+    }
+    if ((t & 63) == 63) wtot[t >> 6] = incl;
+    __syncthreads();
+    int64_t run = incl - acc;
+#pragma unroll
+    for (int k = 0; k < RB_NW; ++k)
+      if (k < (t >> 6)) run += wtot[k];
+    for (int64_t i = lo; i < hi; ++i) {
+      const int64_t x = ts[i];
+      ts[i] = run;
+      run += x;
+    }
+    __syncthreads();  // (wtot is reused by the next array)
+  }
+}
+
+__global__ void __launch_bounds__(RB_TPB) k_rebin_scan_apply(Scan3 S3, const int64_t *tiles) {
+  __shared__ ChunkLds L;
+  int64_t t0, len;
+  const int a = scan3_tile(S3, blockIdx.x, t0, len);
+  int64_t *out = a == 0 ? S3.off_new : (a == 1 ? S3.aoff : S3.chunk_pre);
+  const int64_t base = t0 * RB_CH + (int64_t)RB_PPT * threadIdx.x;
+  uint32_t v[RB_PPT];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j) {
+    v[j] = base + j < len ? scan3_in(S3, a, base + j) : 0u;
+    sum += v[j];
+  }
+  uint32_t total;
+  int64_t run = tiles[blockIdx.x] + (int64_t)block_excl_sum(sum, L, total);
+#pragma unroll
+  for (int j = 0; j < RB_PPT; ++j) {
+    if (base + j < len) out[base + j] = run;
+    run += v[j];
+  }
+  if (base <= len - 1 && len - 1 < base + RB_PPT) out[len] = run;  // the total
 }
 
 // the movers of each chunk into their new group's arrival list (unordered:
@@ -266,7 +357,7 @@ __global__ void k_rebin_lists(const uint32_t *chunk_cnt, const int32_t *mq_p,
 // same count `below` of arrivals before it, and a stayer at p goes to
 //   sbase + p - (movers before p),
 //   sbase = off_new - o0 + (movers before o0) + below.
-// A group whose offsets are inconsistent (reported by k_rebin_check) places
+// A group whose offsets are inconsistent (reported by k_rebin_prep) places
 // nobody: sbase = kNoGroup.
 constexpr int64_t kNoGroup = INT64_MIN;
 
@@ -518,18 +609,21 @@ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 }  // namespace
 
-hipError_t launch_scan(const uint32_t *counts, int64_t m, int64_t *tiles, int64_t *offsets,
-                       hipStream_t s);
-
 // scratch of launch_rebin: the mover queue (position, new group) and the
-// arrival lists, int32[n] each; per chunk of 2048 positions its first
+// arrival lists, int32[n] each; per chunk of RB_CH positions its first
 // group, mover count and the scan of the counts; per group the leaver,
-// arrival, slot and start counters, the arrival offsets and the stayer base
+// arrival, slot and start counters, the arrival offsets and the stayer base.
+// `tiles` holds rebin_tiles_needed(n, m) entries.
 size_t rebin_scratch_bytes(int64_t n, int64_t m) {
   const size_t nn = (size_t)(n > 0 ? n : 1), mm = (size_t)(m > 0 ? m : 1);
   const size_t nch = (nn + RB_CH - 1) / RB_CH;
   return 3 * align256(4 * nn) + 2 * align256(4 * nch) + align256(8 * (nch + 1)) +
-         5 * align256(4 * mm) + align256(8 * (mm + 1)) + align256(8 * mm);
+         4 * align256(4 * mm) + align256(8 * (mm + 1)) + align256(8 * mm);
+}
+
+int64_t rebin_tiles_needed(int64_t n, int64_t m) {
+  const int64_t nch = (n + RB_CH - 1) / RB_CH;
+  return 2 * ((m + RB_CH - 1) / RB_CH) + (nch + RB_CH - 1) / RB_CH + 1;
 }
 
 hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
@@ -553,28 +647,24 @@ hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const 
   uint32_t *leave = reinterpret_cast<uint32_t *>(take(4 * mm));
   uint32_t *arrive = reinterpret_cast<uint32_t *>(take(4 * mm));
   uint32_t *acur = reinterpret_cast<uint32_t *>(take(4 * mm));
-  uint32_t *cnt = reinterpret_cast<uint32_t *>(take(4 * mm));
   uint32_t *gstart = reinterpret_cast<uint32_t *>(take(4 * mm));
   int64_t *aoff = reinterpret_cast<int64_t *>(take(8 * (mm + 1)));
   int64_t *sbase = reinterpret_cast<int64_t *>(take(8 * mm));
 
-  hipError_t e;
-  hipLaunchKernelGGL(k_rebin_zero, dim3(grid_of(m > nch ? m : nch)), dim3(256), 0, s, m, nch,
-                     leave, arrive, acur, gstart, chunk_g0);
-  hipLaunchKernelGGL(k_rebin_check, dim3(grid_of(m)), dim3(256), 0, s, off, m, n, err);
-  if (n > 0) {
-    hipLaunchKernelGGL(k_rebin_chunk_starts, dim3(grid_of(m)), dim3(256), 0, s, m, n, off, nch,
-                       chunk_g0);
+  const int64_t nt0 = (m + RB_CH - 1) / RB_CH, nt2 = (nch + RB_CH - 1) / RB_CH;
+  const Scan3 S3{off, leave, arrive, chunk_cnt, m, nch, nt0, n > 0 ? nt0 : 0, n > 0 ? nt2 : 0,
+                 off_new, aoff, chunk_pre};
+  hipLaunchKernelGGL(k_rebin_prep, dim3(grid_of(m)), dim3(256), 0, s, m, n, off, nch, leave,
+                     arrive, acur, gstart, chunk_g0, err);
+  if (n > 0)
     hipLaunchKernelGGL(k_rebin_mark, dim3((unsigned)nch), dim3(RB_TPB), 0, s, n, m, S, n_cells,
                        off, cells_new, chunk_g0, mq_p, mq_g, chunk_cnt, gstart, leave, arrive,
                        err);
-  }
-  hipLaunchKernelGGL(k_rebin_counts, dim3(grid_of(m)), dim3(256), 0, s, m, off, leave, arrive,
-                     cnt);
-  if ((e = launch_scan(cnt, m, tiles, off_new, s)) != hipSuccess) return e;
+  const int64_t ntt = S3.nt0 + S3.nt1 + S3.nt2;
+  hipLaunchKernelGGL(k_rebin_scan_tiles, dim3((unsigned)ntt), dim3(RB_TPB), 0, s, S3, tiles);
+  hipLaunchKernelGGL(k_rebin_scan_sums, dim3(1), dim3(RB_TPB), 0, s, S3, tiles);
+  hipLaunchKernelGGL(k_rebin_scan_apply, dim3((unsigned)ntt), dim3(RB_TPB), 0, s, S3, tiles);
   if (n > 0) {
-    if ((e = launch_scan(arrive, m, tiles, aoff, s)) != hipSuccess) return e;
-    if ((e = launch_scan(chunk_cnt, nch, tiles, chunk_pre, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_rebin_lists, dim3((unsigned)nch), dim3(256), 0, s, chunk_cnt, mq_p, mq_g,
                        aoff, acur, alist);
     hipLaunchKernelGGL(k_rebin_place_arrivals, dim3(grid_of(m)), dim3(256), 0, s, m, n, off,
