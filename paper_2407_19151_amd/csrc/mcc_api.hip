@@ -928,6 +928,36 @@ static mcc_status plan_enqueue_step(mcc_plan *pl, hipStream_t s) {
   return MCC_OK;
 }
 
+// A plan's bucket work lists, largest cell first (ties by cell index), once
+// at plan creation.  A persistent bucket kernel claims its cells in list
+// order, so the last cells claimed are then the smallest and the grid drains
+// evenly.  Cells are independent (their random numbers are keyed by cell),
+// so the order changes no result.
+static hipError_t order_largest_first(mcc_plan *pl, const int64_t *offsets, int32_t n_cells,
+                                      int32_t S) {
+  std::vector<int64_t> off((size_t)n_cells * S + 1);
+  hipError_t e = hipMemcpy(off.data(), offsets, sizeof(int64_t) * off.size(),
+                           hipMemcpyDeviceToHost);
+  std::vector<int32_t> list;
+  for (int b = 0; b < NBUCKET && e == hipSuccess; ++b) {
+    const uint32_t k = pl->hcount[b];
+    if (k < 2) continue;
+    int32_t *dl = pl->lists.as<int32_t>() + (int64_t)b * n_cells;
+    list.resize(k);
+    e = hipMemcpy(list.data(), dl, sizeof(int32_t) * k, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) break;
+    auto size = [&](int32_t c) {
+      return off[(size_t)(c + 1) * S] - off[(size_t)c * S];
+    };
+    std::sort(list.begin(), list.end(), [&](int32_t x, int32_t y) {
+      const int64_t sx = size(x), sy = size(y);
+      return sx > sy || (sx == sy && x < y);
+    });
+    e = hipMemcpy(dl, list.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice);
+  }
+  return e;
+}
+
 mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_cells,
                            int32_t n_species, const int64_t *offsets, const double *weights,
                            double *vx, double *vy, double *vz, const double *cell_volume,
@@ -966,6 +996,7 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess)
     e = hipMemcpy(pl->hcount, pl->counts.p, sizeof(pl->hcount), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && n_cells > 0) e = order_largest_first(pl, offsets, n_cells, n_species);
   if (e != hipSuccess) {
     mcc_plan_destroy(pl);
     return from_hip(e);
