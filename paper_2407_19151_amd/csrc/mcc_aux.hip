@@ -112,25 +112,27 @@ __global__ void k_scan_tiles(const uint32_t *in, int64_t m, int64_t *tile_sums) 
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = red[0];
 }
 
-// exclusive scan of the tile sums in one workgroup (serial chunks per thread)
+// exclusive scan of the tile sums in one workgroup: serial chunks per
+// thread, the chunk sums scanned by shuffles in each wave and across waves
 __global__ void k_scan_tile_sums(int64_t *tile_sums, int64_t ntiles) {
-  __shared__ int64_t part[SCAN_TPB];
+  __shared__ int64_t wtot[SCAN_TPB / WAVE];
+  const int t = threadIdx.x;
   const int64_t per = (ntiles + SCAN_TPB - 1) / SCAN_TPB;
-  const int64_t lo = threadIdx.x * per, hi = lo + per < ntiles ? lo + per : ntiles;
+  const int64_t lo = t * per, hi = lo + per < ntiles ? lo + per : ntiles;
   int64_t acc = 0;
   for (int64_t i = lo; i < hi; ++i) acc += tile_sums[i];
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int i = 0; i < SCAN_TPB; ++i) {
-      const int64_t x = part[i];
-      part[i] = run;
-      run += x;
-    }
+  int64_t incl = acc;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int64_t y = __shfl_up(incl, d);
+    if ((t & (WAVE - 1)) >= d) incl += y;
   }
+  if ((t & (WAVE - 1)) == WAVE - 1) wtot[t / WAVE] = incl;
   __syncthreads();
-  int64_t run = part[threadIdx.x];
+  int64_t run = incl - acc;
+#pragma unroll
+  for (int k = 0; k < SCAN_TPB / WAVE; ++k)
+    if (k < t / WAVE) run += wtot[k];
   for (int64_t i = lo; i < hi; ++i) {
     const int64_t x = tile_sums[i];
     tile_sums[i] = run;
@@ -139,11 +141,11 @@ __global__ void k_scan_tile_sums(int64_t *tile_sums, int64_t ntiles) {
 }
 
 // a tile's prefix sums: each thread sums its SCAN_PPT consecutive entries,
-// the thread sums are scanned in LDS (log2 SCAN_TPB doubling steps), and
+// the thread sums are scanned by shuffles in each wave and across waves, and
 // each thread writes its entries' offsets
 __global__ void k_scan_apply(const uint32_t *in, int64_t m, const int64_t *tile_off,
                              int64_t *out) {
-  __shared__ int64_t part[SCAN_TPB];
+  __shared__ int64_t wtot[SCAN_TPB / WAVE];
   const int t = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)t * SCAN_PPT;
   uint32_t v[SCAN_PPT];
@@ -153,15 +155,18 @@ __global__ void k_scan_apply(const uint32_t *in, int64_t m, const int64_t *tile_
     v[j] = base + j < m ? in[base + j] : 0u;
     sum += v[j];
   }
-  part[t] = sum;
-  __syncthreads();
-  for (int d = 1; d < SCAN_TPB; d <<= 1) {
-    const int64_t x = t >= d ? part[t - d] : 0;
-    __syncthreads();
-    part[t] += x;
-    __syncthreads();
+  int64_t incl = sum;
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const int64_t y = __shfl_up(incl, d);
+    if ((t & (WAVE - 1)) >= d) incl += y;
   }
-  int64_t run = tile_off[blockIdx.x] + part[t] - sum;
+  if ((t & (WAVE - 1)) == WAVE - 1) wtot[t / WAVE] = incl;
+  __syncthreads();
+  int64_t run = tile_off[blockIdx.x] + incl - sum;
+#pragma unroll
+  for (int k = 0; k < SCAN_TPB / WAVE; ++k)
+    if (k < t / WAVE) run += wtot[k];
 #pragma unroll
   for (int j = 0; j < SCAN_PPT; ++j) {
     if (base + j < m) out[base + j] = run;
