@@ -113,10 +113,10 @@ def copy_calibration(mib):
 
 
 def kernel_source_hash():
-    """sha256 over the sources the collide kernels are built from (their
-    instantiation units, the headers they include and the public header):
-    counters taken from other sources do not describe the kernels that run
-    now."""
+    """sha256 over the code the collide kernels are built from (their
+    instantiation units, the headers they include and the public header;
+    comments aside): counters taken from other code do not describe the
+    kernels that run now."""
     from paper_2407_19151_amd import profile_summary
     return profile_summary.source_hash()
 

@@ -26,11 +26,20 @@ KNAME = re.compile(r"collide_kernel<(\d+), (\d+), (float|double), false, (\d), f
 KERNEL_HEADERS = ("mcc_collide.hpp", "mcc_device.hpp", "mcc_kernel_args.hpp", "mcc_variants.hpp")
 
 
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
+def code_text(src: str) -> str:
+    """C/C++ source with its comments removed and whitespace collapsed: what
+    the compiler sees, so a change to a comment keeps the digest."""
+    return " ".join(_COMMENT.sub(" ", src).split())
+
+
 def source_hash() -> str:
-    """sha256 over the sources the collide kernels are built from: their
-    instantiation units (mcc_collide_*.hip), the headers those include and
-    the public header (the digest bench.py checks before it reports the
-    counters)."""
+    """sha256 over the code (comments aside) the collide kernels are built
+    from: their instantiation units (mcc_collide_*.hip), the headers those
+    include and the public header (the digest bench.py checks before it
+    reports the counters)."""
     h = hashlib.sha256()
     d = os.path.join(HERE, "csrc")
     files = sorted(f for f in os.listdir(d)
@@ -39,7 +48,7 @@ def source_hash() -> str:
     paths.append(os.path.join(os.path.dirname(HERE), "include", "mcc.h"))
     for path in paths:
         h.update(os.path.basename(path).encode())
-        h.update(open(path, "rb").read())
+        h.update(code_text(open(path, encoding="utf-8").read()).encode())
     return h.hexdigest()
 
 
@@ -106,7 +115,7 @@ def traffic(fetch_dir, write_dir, cal_fetch_dir, cal_write_dir, commands, copy_k
               "WRITE_SIZE %.0f KiB" % (copy_kib, cf, cw),
               "# bytes = fetch_kib * 1024 * fetch_factor + write_kib * 1024 * write_factor "
               "(averages over all dispatches)",
-              "# bench.py reports these only while source_sha256 matches the sources of the collide "
+              "# bench.py reports these only while source_sha256 matches the code of the collide "
               "kernels",
               "source_sha256 " + source_hash(),
               "fetch_factor %.4f" % ff, "write_factor %.4f" % wf]
