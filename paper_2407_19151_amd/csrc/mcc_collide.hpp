@@ -819,6 +819,12 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
 
   for (uint32_t li = q + NQ * (blockIdx.x / NQ); li < count;) {
     MCC_PHASE(0);  // header and staging
+    // Wave priority: the phases that end in workgroup barriers (staging,
+    // shuffles, reductions, cut-off, corrections) run at priority 1, the pair
+    // scatter, long runs of arithmetic between two barriers, at 0.  A SIMD then
+    // issues first for the waves that hold a barrier of their cell, and fills
+    // the gaps with other cells' scatter.
+    __builtin_amdgcn_s_setprio(1);
     const int cell = A.cell_list[li];
     // the next entry, claimed now and needed only when this cell is done
     uint32_t claim = 0;
@@ -1060,6 +1066,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       //                 rounds; the regular pairs (L3,L4),... in round 0
       //  inter        : pair k = (big[k], small[k mod N_min]) in rounds of N_min
       MCC_PHASE(2);  // scatter
+      __builtin_amdgcn_s_setprio(0);
       const uint32_t c3p = ctr3(step, k, PURPOSE_PAIR);
       const bool abig = na >= nb;
       const int Nmax = abig ? na : nb, Nmin = abig ? nb : na;
@@ -1195,6 +1202,7 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       }
 
       MCC_PHASE(3);  // momentum restore and energy sums
+      __builtin_amdgcn_s_setprio(1);
       if (!A.corr) continue;
 
       auto in_a = [&](int e) { return (unsigned)(e - oa) < (unsigned)na; };
