@@ -53,16 +53,20 @@ __global__ void k_inc_u64(uint64_t *p) {
 
 // Work lists: cell c of size n goes to the first bucket whose capacity holds
 // it.  lists[b * n_cells + i], counts[b].  Empty cells get cell_corr = 0.
-// The slots are claimed once per wave and bucket (one atomic for all lanes
-// of the wave that go there, in lane order): a per-cell atomic on seven
-// counters would serialize the whole grid on them.
-__global__ void k_bucket_cells(const int64_t *offsets, int32_t n_cells, int32_t S, int64_t n,
-                               int32_t *lists, uint32_t *counts, int32_t *cell_corr,
-                               int32_t *err) {
+// A workgroup counts its cells per bucket in LDS (one LDS atomic per wave and
+// bucket), reserves its slots with one global atomic per bucket, and each
+// wave writes its cells after its own slots: per-wave global atomics on the
+// seven counters would serialize the grid on them.
+__global__ void __launch_bounds__(256)
+    k_bucket_cells(const int64_t *offsets, int32_t n_cells, int32_t S, int64_t n,
+                   int32_t *lists, uint32_t *counts, int32_t *cell_corr, int32_t *err) {
+  __shared__ uint32_t lcount[NBUCKET], lbase[NBUCKET];
   const int lane = threadIdx.x & (WAVE - 1);
   const uint64_t below = (1ull << lane) - 1ull;
   for (int64_t c0 = blockIdx.x * (int64_t)blockDim.x; c0 < n_cells;
        c0 += (int64_t)gridDim.x * blockDim.x) {
+    if (threadIdx.x < NBUCKET) lcount[threadIdx.x] = 0u;
+    __syncthreads();
     const int64_t c = c0 + threadIdx.x;
     int b = -1;  // this lane's bucket, or -1: no list entry
     if (c < n_cells) {
@@ -82,15 +86,23 @@ __global__ void k_bucket_cells(const int64_t *offsets, int32_t n_cells, int32_t 
         }
       }
     }
+    uint32_t slot = 0;  // the lane's slot among the workgroup's cells of bucket b
     for (int k = 0; k < NBUCKET; ++k) {
       const uint64_t m = __ballot(b == k);
       if (m == 0) continue;  // (uniform over the wave)
       const int leader = __ffsll((unsigned long long)m) - 1;
       uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(&counts[k], (uint32_t)__popcll(m));
+      if (lane == leader) base = atomicAdd(&lcount[k], (uint32_t)__popcll(m));
       base = __shfl(base, leader);
-      if (b == k) lists[(int64_t)k * n_cells + base + __popcll(m & below)] = (int32_t)c;
+      if (b == k) slot = base + (uint32_t)__popcll(m & below);
     }
+    __syncthreads();
+    if (threadIdx.x < NBUCKET)
+      lbase[threadIdx.x] =
+          lcount[threadIdx.x] ? atomicAdd(&counts[threadIdx.x], lcount[threadIdx.x]) : 0u;
+    __syncthreads();
+    if (b >= 0) lists[(int64_t)b * n_cells + lbase[b] + slot] = (int32_t)c;
+    __syncthreads();  // (lcount and lbase are reused by the next chunk)
   }
 }
 
