@@ -395,9 +395,8 @@ mcc_status mcc_rebin_out(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t n_spe
  * device and each bucket's cells largest first (on the host: the offsets and
  * the lists are copied there once, so the last cells a bucket's persistent
  * grid claims are its smallest), picks threads-per-cell for each bucket
- * (autotune = 1 times the
- * candidates on this population; 0 uses the built-in table), and captures
- * one step into a HIP graph.  mcc_plan_run replays it n_steps times with
+ * (autotune = 1 times the candidates on this population; 0 uses the
+ * built-in table), and captures one step into a HIP graph.  mcc_plan_run replays it n_steps times with
  * steps first_step, first_step+1, ...  The plan holds the offsets and the
  * weights by pointer: if they change, destroy and re-create it.  With the
  * moment correction on, it also computes once what depends on the weights
