@@ -58,12 +58,16 @@ int64_t rebin_tiles_needed(int64_t n, int64_t m);
 hipError_t launch_rebin(int64_t n, int64_t m, int32_t S, int32_t n_cells, const int64_t *off,
                         const int32_t *cells_new, int64_t *off_new, int32_t *perm,
                         void *scratch, int64_t *tiles, int32_t *err, hipStream_t s);
+hipError_t launch_gather_rec(int64_t n, const int32_t *perm, const double *w, const double *vx,
+                             const double *vy, const double *vz, void *rec, double *gw,
+                             double *gx, double *gy, double *gz, hipStream_t s);
+hipError_t launch_scatter_back_rec(int64_t n, const int32_t *perm, const double *gw,
+                                   const double *gx, const double *gy, const double *gz,
+                                   void *rec, double *vx, double *vy, double *vz,
+                                   hipStream_t s);
 hipError_t launch_gather(int64_t n, const int32_t *perm, const double *w, const double *vx,
                          const double *vy, const double *vz, double *gw, double *gx, double *gy,
                          double *gz, hipStream_t s);
-hipError_t launch_scatter_back(int64_t n, const int32_t *perm, const double *gx,
-                               const double *gy, const double *gz, double *vx, double *vy,
-                               double *vz, hipStream_t s);
 struct AdjointArgs;
 hipError_t launch_adjoint(const AdjointArgs &base, bool fp32, const int32_t *lists,
                           const uint32_t *counts, int32_t n_cells, int b, int tpc, int cap,
@@ -148,7 +152,7 @@ struct mcc_ctx {
   // launches of one context must not overlap)
   DevBuf work;
   // unsorted entry
-  DevBuf tiles, off, perm, gw, gx, gy, gz;
+  DevBuf tiles, off, perm, gw, gx, gy, gz, rec;
   DevBuf bin_k0, bin_k1, bin_v0, bin_v1, bin_hist, bin_pos;  // radix-sort scratch
   // reverse-mode form: per-workgroup scratch (cells up to 4096 particles,
   // and above), per-cell lnL adjoints
@@ -522,7 +526,7 @@ void mcc_destroy(mcc_ctx *ctx) {
   ctx->big.release();
   for (DevBuf *b : {&ctx->lists, &ctx->counts, &ctx->tiles, &ctx->off, &ctx->perm,
                     &ctx->bin_k0, &ctx->bin_k1, &ctx->bin_v0, &ctx->bin_v1, &ctx->bin_hist,
-                    &ctx->bin_pos, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->n97,
+                    &ctx->bin_pos, &ctx->gw, &ctx->gx, &ctx->gy, &ctx->gz, &ctx->rec, &ctx->n97,
                     &ctx->work, &ctx->rb, &ctx->adj_small, &ctx->adj_big,
                     &ctx->adj_part})
     b->release();
@@ -892,14 +896,14 @@ mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int3
   if (!ctx->off.ensure(sizeof(int64_t) * (size_t)(m + 1)) ||
       !ctx->perm.ensure(sizeof(int32_t) * nn) || !ctx->gw.ensure(sizeof(double) * nn) ||
       !ctx->gx.ensure(sizeof(double) * nn) || !ctx->gy.ensure(sizeof(double) * nn) ||
-      !ctx->gz.ensure(sizeof(double) * nn))
+      !ctx->gz.ensure(sizeof(double) * nn) || !ctx->rec.ensure(32 * nn))
     return MCC_ERR_OOM;
   st = bin_into(ctx, n, cells, species_id, n_cells, n_species, ctx->off.as<int64_t>(),
                 ctx->perm.as<int32_t>());
   if (st != MCC_OK) return st;
-  HIP_TRY(launch_gather(n, ctx->perm.as<int32_t>(), weights, vx, vy, vz, ctx->gw.as<double>(),
-                        ctx->gx.as<double>(), ctx->gy.as<double>(), ctx->gz.as<double>(),
-                        ctx->stream));
+  HIP_TRY(launch_gather_rec(n, ctx->perm.as<int32_t>(), weights, vx, vy, vz, ctx->rec.p,
+                            ctx->gw.as<double>(), ctx->gx.as<double>(), ctx->gy.as<double>(),
+                            ctx->gz.as<double>(), ctx->stream));
   const bool v = ctx->validate;
   ctx->validate = false;
   st = mcc_collide_sorted(ctx, n, n_cells, n_species, ctx->off.as<int64_t>(),
@@ -908,9 +912,9 @@ mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int3
                           coll, dt, coulomb_log, seed, step, p, stats, cell_corr_pairs);
   ctx->validate = v;
   if (st != MCC_OK) return st;
-  HIP_TRY(launch_scatter_back(n, ctx->perm.as<int32_t>(), ctx->gx.as<double>(),
-                              ctx->gy.as<double>(), ctx->gz.as<double>(), vx, vy, vz,
-                              ctx->stream));
+  HIP_TRY(launch_scatter_back_rec(n, ctx->perm.as<int32_t>(), ctx->gw.as<double>(),
+                                  ctx->gx.as<double>(), ctx->gy.as<double>(),
+                                  ctx->gz.as<double>(), ctx->rec.p, vx, vy, vz, ctx->stream));
   return finish(ctx);
 }
 

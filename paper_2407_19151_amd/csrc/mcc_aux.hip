@@ -384,16 +384,53 @@ __global__ void k_gather(int64_t n, const int32_t *perm, const double *w, const 
   }
 }
 
-__global__ void k_scatter_back(int64_t n, const int32_t *perm, const double *gx,
-                               const double *gy, const double *gz, double *vx, double *vy,
-                               double *vz) {
+// The unsorted entry's payload moves through 32-byte records (w, vx, vy, vz)
+// of a context-owned array in the caller's order: a particle's random access
+// is then one aligned 32-byte record, one memory segment, instead of an 8-byte
+// word in each of four arrays.  Packing and unpacking stream.
+struct alignas(32) Rec4 {
+  double w, x, y, z;
+};
+
+__global__ void k_pack_rec(int64_t n, const double *w, const double *vx, const double *vy,
+                           const double *vz, Rec4 *rec) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    rec[i] = Rec4{w[i], vx[i], vy[i], vz[i]};
+}
+
+__global__ void k_gather_rec(int64_t n, const int32_t *perm, const Rec4 *rec, double *gw,
+                             double *gx, double *gy, double *gz) {
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
        j += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = perm[j];
     if (i < 0 || i >= n) continue;
-    vx[i] = gx[j];
-    vy[i] = gy[j];
-    vz[i] = gz[j];
+    const Rec4 r = rec[i];
+    gw[j] = r.w;
+    gx[j] = r.x;
+    gy[j] = r.y;
+    gz[j] = r.z;
+  }
+}
+
+// whole records back (the weight unchanged), then the velocities out
+__global__ void k_scatter_rec(int64_t n, const int32_t *perm, const double *gw, const double *gx,
+                              const double *gy, const double *gz, Rec4 *rec) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = perm[j];
+    if (i < 0 || i >= n) continue;
+    rec[i] = Rec4{gw[j], gx[j], gy[j], gz[j]};
+  }
+}
+
+__global__ void k_unpack_v(int64_t n, const Rec4 *rec, double *vx, double *vy, double *vz) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const Rec4 r = rec[i];
+    vx[i] = r.x;
+    vy[i] = r.y;
+    vz[i] = r.z;
   }
 }
 
@@ -575,13 +612,29 @@ hipError_t launch_gather(int64_t n, const int32_t *perm, const double *w, const 
   return hipGetLastError();
 }
 
-hipError_t launch_scatter_back(int64_t n, const int32_t *perm, const double *gx,
-                               const double *gy, const double *gz, double *vx, double *vy,
-                               double *vz, hipStream_t s) {
+// gather through records: rec (32 * n bytes, 32-byte aligned) is scratch
+hipError_t launch_gather_rec(int64_t n, const int32_t *perm, const double *w, const double *vx,
+                             const double *vy, const double *vz, void *rec, double *gw,
+                             double *gx, double *gy, double *gz, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_scatter_back, dim3(grid_for(n, 256)), dim3(256), 0, s, n, perm, gx, gy,
-                     gz, vx, vy, vz);
+  Rec4 *r = static_cast<Rec4 *>(rec);
+  hipLaunchKernelGGL(k_pack_rec, dim3(grid_for(n, 256)), dim3(256), 0, s, n, w, vx, vy, vz, r);
+  hipLaunchKernelGGL(k_gather_rec, dim3(grid_for(n, 256)), dim3(256), 0, s, n, perm, r, gw, gx,
+                     gy, gz);
   return hipGetLastError();
 }
+
+hipError_t launch_scatter_back_rec(int64_t n, const int32_t *perm, const double *gw,
+                                   const double *gx, const double *gy, const double *gz,
+                                   void *rec, double *vx, double *vy, double *vz,
+                                   hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  Rec4 *r = static_cast<Rec4 *>(rec);
+  hipLaunchKernelGGL(k_scatter_rec, dim3(grid_for(n, 256)), dim3(256), 0, s, n, perm, gw, gx, gy,
+                     gz, r);
+  hipLaunchKernelGGL(k_unpack_v, dim3(grid_for(n, 256)), dim3(256), 0, s, n, r, vx, vy, vz);
+  return hipGetLastError();
+}
+
 
 }  // namespace mcc
