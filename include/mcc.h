@@ -251,7 +251,9 @@ mcc_status mcc_collide_sorted_noalloc(mcc_ctx *ctx, int64_t n, int32_t n_cells,
  * One step on particles in any order: cells, species_id are device
  * int32[n].  Particles are grouped by (cell, species) keeping ascending
  * index order inside each group, the sorted step is applied, and the
- * velocities are written back in place.  Same other arguments.
+ * velocities are written back in place.  Same other arguments.  The context
+ * grows scratch of about 84 bytes per particle for it (the grouping, the
+ * payload in grouped order and in 32-byte records) plus the binning's.
  */
 mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells,
                        const int32_t *species_id, int32_t n_cells,
