@@ -252,8 +252,8 @@ mcc_status mcc_collide_sorted_noalloc(mcc_ctx *ctx, int64_t n, int32_t n_cells,
  * int32[n].  Particles are grouped by (cell, species) keeping ascending
  * index order inside each group, the sorted step is applied, and the
  * velocities are written back in place.  Same other arguments.  The context
- * grows scratch of about 84 bytes per particle for it (the grouping, the
- * payload in grouped order and in 32-byte records) plus the binning's.
+ * grows scratch of about 68 bytes per particle for it (the grouping, the
+ * payload in grouped order and in 32-byte records) plus 16 for the binning.
  */
 mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells,
                        const int32_t *species_id, int32_t n_cells,
