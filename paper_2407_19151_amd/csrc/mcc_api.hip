@@ -921,13 +921,35 @@ mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int3
 // ---------------------------------------------------------------------------
 // Batched plan
 // ---------------------------------------------------------------------------
-static mcc_status plan_enqueue_step(mcc_plan *pl, hipStream_t s) {
+// One step into the graph being captured on s: the bucket kernels, the
+// bucket of the largest cells first.  The 4096 bucket runs on a branch
+// (side stream sb, forked by event fork and joined by event join) beside the
+// 2048 bucket: its cells take a whole CU's LDS each and drain unevenly, and
+// the 2048 cells fill the CUs it leaves.  Every other bucket runs alone: cells
+// of different sizes sharing CUs slowed the step (2-7 %).
+static mcc_status plan_enqueue_step(mcc_plan *pl, hipStream_t s, hipStream_t sb,
+                                    hipEvent_t fork, hipEvent_t join) {
   // counters are reset by kernels (no memset nodes in the graph)
   if (pl->stats) HIP_TRY(launch_zero_stats(pl->stats, s));
-  mcc_status st = launch_buckets(pl->ctx, pl->big, pl->args, pl->mode, pl->n_cells,
-                                 pl->lists.as<int32_t>(), pl->counts.as<uint32_t>(), pl->variant,
-                                 s, pl->hcount);
-  if (st != MCC_OK) return st;
+  constexpr int kSide = 5, kBeside = 4;  // the 4096 bucket, beside the 2048 bucket
+  static_assert(kBucketCap[kSide] == 4096 && kBucketCap[kBeside] == 2048, "bucket table");
+  const bool branch = pl->hcount[kSide] > 0 && pl->hcount[kBeside] > 0;
+  if (branch) {
+    HIP_TRY(hipEventRecord(fork, s));
+    HIP_TRY(hipStreamWaitEvent(sb, fork, 0));
+  }
+  for (int b = NBUCKET - 1; b >= 0; --b) {
+    if (pl->hcount[b] == 0) continue;
+    const int v = pl->variant[b] >= 0 ? pl->variant[b] : default_variant(pl->mode, b);
+    const mcc_status st =
+        launch_bucket(pl->ctx, pl->big, pl->args, pl->mode, pl->n_cells, pl->lists.as<int32_t>(),
+                      pl->counts.as<uint32_t>(), b, v, (branch && b == kSide) ? sb : s);
+    if (st != MCC_OK) return st;
+    if (branch && b == kBeside) {
+      HIP_TRY(hipEventRecord(join, sb));
+      HIP_TRY(hipStreamWaitEvent(s, join, 0));
+    }
+  }
   HIP_TRY(launch_inc_u64(pl->step.as<uint64_t>(), s));
   return MCC_OK;
 }
@@ -1115,16 +1137,24 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
     pl->args.prep_word = W.prep_word;
   }
   // capture one step into a graph: stats reset, bucket kernels, step += 1
-  hipStream_t cs;
+  // (default-priority streams; the side stream only carries a branch)
+  hipStream_t cs = nullptr, sb = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&sb, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    st = plan_enqueue_step(pl, cs);
+    st = plan_enqueue_step(pl, cs, sb, fork, join);
     hipError_t e2 = hipStreamEndCapture(cs, &pl->graph);
     if (st == MCC_OK && e2 != hipSuccess) st = from_hip(e2);
     if (st == MCC_OK) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
   }
-  (void)hipStreamDestroy(cs);
+  if (join) (void)hipEventDestroy(join);
+  if (fork) (void)hipEventDestroy(fork);
+  if (sb) (void)hipStreamDestroy(sb);
+  if (cs) (void)hipStreamDestroy(cs);
   if (e != hipSuccess || st != MCC_OK) {
     mcc_plan_destroy(pl);
     return st != MCC_OK ? st : from_hip(e);
