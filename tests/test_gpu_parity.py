@@ -373,7 +373,10 @@ def test_deterministic_reruns(ctx):
 def test_plan_graph_replay_equals_plain_steps(ctx):
     """A plan with the default variants replays exactly the plain steps
     (bitwise); an autotuned plan agrees to the parity bar (its per-cell sums
-    may run with another threads-per-cell, hence another rounding order)."""
+    may run with another threads-per-cell, hence another rounding order).
+    The population has cells in the 2048 and the 4096 buckets, so the graph's
+    branch (the 4096 bucket beside the 2048 one) is part of the replay."""
+    import json
     from paper_2407_19151_amd import runner
     wl = W.config3(n_cells=512)
     dw1 = runner.DeviceWorkload(wl)
@@ -382,6 +385,8 @@ def test_plan_graph_replay_equals_plain_steps(ctx):
     plan = runner.make_plan(ctx, dw1, autotune=False)
     tuned = runner.make_plan(ctx, dw3, autotune=True)
     try:
+        cells = {b["max_cell"]: b["cells"] for b in json.loads(plan.describe())["buckets"]}
+        assert cells[2048] > 0 and cells[4096] > 0, cells
         print(tuned.describe(), flush=True)
         plan.run(first_step=5, n_steps=3)
         tuned.run(first_step=5, n_steps=1)
