@@ -138,9 +138,20 @@ const void *const *kernel_table(int mode) {
 
 }  // namespace
 
+// A side stream and two events (default priority, created once) that let the
+// 4096 bucket run on a branch beside the 2048 bucket: its cells take a whole
+// CU's LDS each and drain unevenly, and the 2048 cells fill the CUs it leaves.
+// Every other bucket runs alone: cells of different sizes sharing CUs slowed
+// the step (2-7 %).
+struct Branch {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 struct mcc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  Branch branch;  // the per-call steps' branch (launch_buckets)
   int n_cu = 0;
   bool validate = false;
   int32_t *err = nullptr;  // device error word
@@ -353,19 +364,37 @@ mcc_status launch_bucket(mcc_ctx *ctx, BigScratch &big, const CollideArgs &base,
   return MCC_OK;
 }
 
+constexpr int kSideBucket = 5, kBesideBucket = 4;
+static_assert(kBucketCap[kSideBucket] == 4096 && kBucketCap[kBesideBucket] == 2048,
+              "the branch pairs the 4096 and 2048 buckets");
+
 // enqueue the collide kernels of all buckets, largest cells first
 // (host_counts: the buckets' cell counts when known on the host; empty
-// buckets are then not launched)
+// buckets are then not launched).  With br, the 4096 bucket runs on the
+// branch, unless both kernels use global scratch (they would share the
+// large-cell buffer).
 mcc_status launch_buckets(mcc_ctx *ctx, BigScratch &big, const CollideArgs &base, int mode,
                           int32_t n_cells, const int32_t *lists, const uint32_t *counts,
                           const int *variant, hipStream_t stream,
-                          const uint32_t *host_counts = nullptr) {
+                          const uint32_t *host_counts = nullptr, const Branch *br = nullptr) {
+  auto pick = [&](int b) { return variant[b] >= 0 ? variant[b] : default_variant(mode, b); };
+  const bool branch =
+      br && (!host_counts || (host_counts[kSideBucket] > 0 && host_counts[kBesideBucket] > 0)) &&
+      !(variant_of(mode, pick(kSideBucket)).layout == 2 &&
+        variant_of(mode, pick(kBesideBucket)).layout == 2);
+  if (branch) {
+    HIP_TRY(hipEventRecord(br->fork, stream));
+    HIP_TRY(hipStreamWaitEvent(br->side, br->fork, 0));
+  }
   for (int b = NBUCKET - 1; b >= 0; --b) {
     if (host_counts && host_counts[b] == 0) continue;
-    const int v = variant[b] >= 0 ? variant[b] : default_variant(mode, b);
-    const mcc_status st =
-        launch_bucket(ctx, big, base, mode, n_cells, lists, counts, b, v, stream);
+    const mcc_status st = launch_bucket(ctx, big, base, mode, n_cells, lists, counts, b, pick(b),
+                                        (branch && b == kSideBucket) ? br->side : stream);
     if (st != MCC_OK) return st;
+    if (branch && b == kBesideBucket) {
+      HIP_TRY(hipEventRecord(br->join, br->side));
+      HIP_TRY(hipStreamWaitEvent(stream, br->join, 0));
+    }
   }
   return MCC_OK;
 }
@@ -489,11 +518,14 @@ mcc_status mcc_create(mcc_ctx **out, int device, void *hip_stream) {
     e = ctx->work.ensure(sizeof(uint32_t) * WORK_QUEUES * WORK_STRIDE * NBUCKET)
             ? hipSuccess
             : hipErrorOutOfMemory;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->branch.side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->branch.fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->branch.join, hipEventDisableTiming);
   if (e == hipSuccess)
     e = hipMemset(ctx->work.p, 0, sizeof(uint32_t) * WORK_QUEUES * WORK_STRIDE * NBUCKET);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
-    delete ctx;
+    mcc_destroy(ctx);  // (releases what was created)
     return from_hip(e);
   }
 #ifdef MCC_PHASE_TIMING
@@ -531,6 +563,10 @@ void mcc_destroy(mcc_ctx *ctx) {
                     &ctx->adj_part})
     b->release();
   if (ctx->err) (void)hipFree(ctx->err);
+  if (ctx->branch.side) (void)hipStreamSynchronize(ctx->branch.side);
+  if (ctx->branch.join) (void)hipEventDestroy(ctx->branch.join);
+  if (ctx->branch.fork) (void)hipEventDestroy(ctx->branch.fork);
+  if (ctx->branch.side) (void)hipStreamDestroy(ctx->branch.side);
   delete ctx;
 }
 
@@ -593,7 +629,7 @@ mcc_status mcc_collide_sorted(mcc_ctx *ctx, int64_t n, int32_t n_cells, int32_t 
   HIP_TRY(launch_bucket_cells(offsets, n_cells, n_species, n, ctx->lists.as<int32_t>(),
                               ctx->counts.as<uint32_t>(), cell_corr_pairs, ctx->err, s));
   st = launch_buckets(ctx, ctx->big, A, mode_of(p, A), n_cells, ctx->lists.as<int32_t>(),
-                      ctx->counts.as<uint32_t>(), ctx->variant, s);
+                      ctx->counts.as<uint32_t>(), ctx->variant, s, nullptr, &ctx->branch);
   if (st != MCC_OK) return st;
   return finish(ctx);
 }
@@ -921,35 +957,15 @@ mcc_status mcc_collide(mcc_ctx *ctx, int64_t n, const int32_t *cells, const int3
 // ---------------------------------------------------------------------------
 // Batched plan
 // ---------------------------------------------------------------------------
-// One step into the graph being captured on s: the bucket kernels, the
-// bucket of the largest cells first.  The 4096 bucket runs on a branch
-// (side stream sb, forked by event fork and joined by event join) beside the
-// 2048 bucket: its cells take a whole CU's LDS each and drain unevenly, and
-// the 2048 cells fill the CUs it leaves.  Every other bucket runs alone: cells
-// of different sizes sharing CUs slowed the step (2-7 %).
-static mcc_status plan_enqueue_step(mcc_plan *pl, hipStream_t s, hipStream_t sb,
-                                    hipEvent_t fork, hipEvent_t join) {
+// One step into the graph being captured on s (the branch of
+// launch_buckets on the capture's side stream and events)
+static mcc_status plan_enqueue_step(mcc_plan *pl, hipStream_t s, const Branch &br) {
   // counters are reset by kernels (no memset nodes in the graph)
   if (pl->stats) HIP_TRY(launch_zero_stats(pl->stats, s));
-  constexpr int kSide = 5, kBeside = 4;  // the 4096 bucket, beside the 2048 bucket
-  static_assert(kBucketCap[kSide] == 4096 && kBucketCap[kBeside] == 2048, "bucket table");
-  const bool branch = pl->hcount[kSide] > 0 && pl->hcount[kBeside] > 0;
-  if (branch) {
-    HIP_TRY(hipEventRecord(fork, s));
-    HIP_TRY(hipStreamWaitEvent(sb, fork, 0));
-  }
-  for (int b = NBUCKET - 1; b >= 0; --b) {
-    if (pl->hcount[b] == 0) continue;
-    const int v = pl->variant[b] >= 0 ? pl->variant[b] : default_variant(pl->mode, b);
-    const mcc_status st =
-        launch_bucket(pl->ctx, pl->big, pl->args, pl->mode, pl->n_cells, pl->lists.as<int32_t>(),
-                      pl->counts.as<uint32_t>(), b, v, (branch && b == kSide) ? sb : s);
-    if (st != MCC_OK) return st;
-    if (branch && b == kBeside) {
-      HIP_TRY(hipEventRecord(join, sb));
-      HIP_TRY(hipStreamWaitEvent(s, join, 0));
-    }
-  }
+  const mcc_status st =
+      launch_buckets(pl->ctx, pl->big, pl->args, pl->mode, pl->n_cells, pl->lists.as<int32_t>(),
+                     pl->counts.as<uint32_t>(), pl->variant, s, pl->hcount, &br);
+  if (st != MCC_OK) return st;
   HIP_TRY(launch_inc_u64(pl->step.as<uint64_t>(), s));
   return MCC_OK;
 }
@@ -1138,22 +1154,22 @@ mcc_status mcc_plan_create(mcc_ctx *ctx, mcc_plan **plan, int64_t n, int32_t n_c
   }
   // capture one step into a graph: stats reset, bucket kernels, step += 1
   // (default-priority streams; the side stream only carries a branch)
-  hipStream_t cs = nullptr, sb = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t cs = nullptr;
+  Branch br;
   e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&sb, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&br.side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&br.fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&br.join, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    st = plan_enqueue_step(pl, cs, sb, fork, join);
+    st = plan_enqueue_step(pl, cs, br);
     hipError_t e2 = hipStreamEndCapture(cs, &pl->graph);
     if (st == MCC_OK && e2 != hipSuccess) st = from_hip(e2);
     if (st == MCC_OK) e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
   }
-  if (join) (void)hipEventDestroy(join);
-  if (fork) (void)hipEventDestroy(fork);
-  if (sb) (void)hipStreamDestroy(sb);
+  if (br.join) (void)hipEventDestroy(br.join);
+  if (br.fork) (void)hipEventDestroy(br.fork);
+  if (br.side) (void)hipStreamDestroy(br.side);
   if (cs) (void)hipStreamDestroy(cs);
   if (e != hipSuccess || st != MCC_OK) {
     mcc_plan_destroy(pl);
