@@ -148,7 +148,11 @@ const char *mcc_status_string(mcc_status s);
  * stream).  The context owns its workspace (cell work lists, error word,
  * large-cell scratch, the collide kernels' cell-queue counters), grown on
  * demand.  Work enqueued through one context must run in order: the calls of
- * one context share that workspace, so they must not overlap on the device. */
+ * one context share that workspace, so they must not overlap on the device.
+ * The context also creates one side stream (default priority) on which the
+ * sorted step runs the kernel of its 2049-4096-particle cells beside the
+ * 1025-2048 one; it forks from and joins back to the context's stream by
+ * events within the call, so callers see one stream. */
 mcc_status mcc_create(mcc_ctx **ctx, int device, void *hip_stream);
 /* Enqueue later calls on `hip_stream`.  Work already enqueued on the previous
  * stream must be complete (or ordered before the next call) first, since it
