@@ -539,3 +539,31 @@ def test_device_angle_sampler_matches_oracle_over_s_range(ctx, method):
         if abs(oc[i] - ro) > 1e-12 * max(ro, 1e-300) + 1e-15 or abs(st[i] - rs) > 1e-12:
             bad.append(("angle", i, s[i], u0, oc[i], ro, st[i], rs))
     assert not bad, bad[:10]
+
+
+def test_per_call_step_on_a_caller_stream_equals_the_default_stream(ctx):
+    """The sorted step runs the kernel of its 2049-4096-particle cells on the
+    context's side stream beside the 1025-2048 one, forked from and joined to
+    the caller's stream.  Enqueued on a stream of the caller's (default
+    priority), with the caller's own work before and after it on that stream,
+    the step must equal the same step on the default stream, bit for bit, and
+    the caller's later work must see its result."""
+    import torch
+    from paper_2407_19151_amd import runner
+    wl = custom_workload([(1300, 900), (2600, 1300), (700, 600), (90, 40), (2000, 1900)],
+                         seed=16)
+    d0 = runner.DeviceWorkload(wl)
+    d1 = runner.DeviceWorkload(wl)
+    for k in range(3):
+        runner.collide_sorted(ctx, d0, 30 + k, with_stats=False)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        d1.vx.mul_(1.0)  # caller work before the step, on the same stream
+        for k in range(3):
+            runner.collide_sorted(ctx, d1, 30 + k, with_stats=False)
+        after = d1.vx * 1.0  # caller work after the step reads its result
+    s.synchronize()
+    assert ctx.device_error() == 0
+    assert np.array_equal(d0.velocities(), d1.velocities())
+    assert np.array_equal(after.cpu().numpy(), d0.vx.cpu().numpy())
