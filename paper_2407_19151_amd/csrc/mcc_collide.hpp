@@ -475,14 +475,21 @@ __device__ __forceinline__ void shuffle_species(const CellMem &M, int ns, int of
   if (t == 0) *maxocc = 0u;
   __syncthreads();
   const uint64_t nsu = (uint64_t)ns;
-  bucket_rank_sort<TPC, PPT, G, true>(
-      ns, cnt, M.mem, out, wsum, maxocc,
-      [&](int i) -> uint32_t { return (uint32_t)(((uint64_t)key[i] * nsu) >> 32); },
-      [&](int o, int i) -> bool {
-        const uint32_t ko = key[o], ki = key[i];
-        return ko < ki || (ko == ki && o < i);
-      },
-      M.slotbuf, [&](int i) -> int { return i + off; });
+  if constexpr (!G) {
+    key_rank_sort<TPC, PPT>(
+        ns, key, cnt, M.mem, out, wsum,
+        [&](int, uint32_t k) -> uint32_t { return (uint32_t)(((uint64_t)k * nsu) >> 32); },
+        [&](int i) -> int { return i + off; });
+  } else {
+    bucket_rank_sort<TPC, PPT, G, true>(
+        ns, cnt, M.mem, out, wsum, maxocc,
+        [&](int i) -> uint32_t { return (uint32_t)(((uint64_t)key[i] * nsu) >> 32); },
+        [&](int o, int i) -> bool {
+          const uint32_t ko = key[o], ki = key[i];
+          return ko < ki || (ko == ki && o < i);
+        },
+        M.slotbuf, [&](int i) -> int { return i + off; });
+  }
 }
 
 // The random permutations of both species of an inter-species collision in
@@ -516,17 +523,27 @@ __device__ __forceinline__ void shuffle_two(const CellMem &M, int na, int oa, in
   if (t == 0) *maxocc = 0u;
   __syncthreads();
   const uint64_t nau = (uint64_t)na, nbu = (uint64_t)nb;
-  bucket_rank_sort<TPC, PPT, G, true>(
-      n, M.cnt, M.mem, out, wsum, maxocc,
-      [&](int i) -> uint32_t {
-        return i < na ? (uint32_t)(((uint64_t)key[i] * nau) >> 32)
-                      : (uint32_t)na + (uint32_t)(((uint64_t)key[i] * nbu) >> 32);
-      },
-      [&](int o, int i) -> bool {
-        const uint32_t ko = key[o], ki = key[i];
-        return ko < ki || (ko == ki && o < i);
-      },
-      M.slotbuf, [&](int i) -> int { return i < na ? oa + i : ob + (i - na); });
+  if constexpr (!G) {
+    key_rank_sort<TPC, PPT>(
+        n, key, M.cnt, M.mem, out, wsum,
+        [&](int i, uint32_t k) -> uint32_t {
+          return i < na ? (uint32_t)(((uint64_t)k * nau) >> 32)
+                        : (uint32_t)na + (uint32_t)(((uint64_t)k * nbu) >> 32);
+        },
+        [&](int i) -> int { return i < na ? oa + i : ob + (i - na); });
+  } else {
+    bucket_rank_sort<TPC, PPT, G, true>(
+        n, M.cnt, M.mem, out, wsum, maxocc,
+        [&](int i) -> uint32_t {
+          return i < na ? (uint32_t)(((uint64_t)key[i] * nau) >> 32)
+                        : (uint32_t)na + (uint32_t)(((uint64_t)key[i] * nbu) >> 32);
+        },
+        [&](int o, int i) -> bool {
+          const uint32_t ko = key[o], ki = key[i];
+          return ko < ki || (ko == ki && o < i);
+        },
+        M.slotbuf, [&](int i) -> int { return i < na ? oa + i : ob + (i - na); });
+  }
 }
 
 // Descending-weight order of ns particles, stable in list position (Alg. 1,

@@ -587,6 +587,57 @@ __device__ __forceinline__ uint32_t bucket_rank_sort(int n, uint32_t *cnt, uint1
   return occ;
 }
 
+// The bucket-rank sort of the shuffles: items 0..n-1 ordered by (key[i], i)
+// ascending, out[pos] = map(item).  As bucket_rank_sort with ZEROED (cnt[0..n)
+// zero before a barrier), at most PPT items per thread.  Each thread keeps its
+// items' keys in registers; once they are counted, the keys are moved into
+// bucket order over the key array itself (it is not read again), so ranking
+// inside a bucket reads an entry's key and index with two independent loads
+// instead of the index and then its key.
+template <int TPC, int PPT, class BucketF, class MapF>
+__device__ __forceinline__ void key_rank_sort(int n, uint32_t *key, uint32_t *cnt, uint16_t *mem,
+                                              uint16_t *out, uint32_t *wsum, BucketF bucket,
+                                              MapF map) {
+  const int t = threadIdx.x;
+  uint32_t bk[PPT], slot[PPT], kv[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int i = t + j * TPC;
+    if (i < n) {
+      kv[j] = key[i];
+      bk[j] = bucket(i, kv[j]);
+      slot[j] = atomicAdd(&cnt[bk[j]], 1u);
+    }
+  }
+  __syncthreads();
+  block_exclusive_scan<TPC, PPT, false>(cnt, n, wsum);
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int i = t + j * TPC;
+    if (i < n) {
+      const uint32_t pos = cnt[bk[j]] + slot[j];
+      mem[pos] = (uint16_t)i;
+      key[pos] = kv[j];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int i = t + j * TPC;
+    if (i < n) {
+      const uint32_t s0 = cnt[bk[j]], s1 = cnt[bk[j] + 1];
+      uint32_t r = 0;
+      for (uint32_t m = s0; m < s1; ++m) {
+        const uint32_t ko = key[m];
+        const int o = mem[m];
+        r += (ko < kv[j] || (ko == kv[j] && o < i)) ? 1u : 0u;
+      }
+      out[s0 + r] = (uint16_t)map(i);
+    }
+  }
+  __syncthreads();
+}
+
 // Bitonic sort of P = 2^k item ids in LDS under a strict total order
 // `less(a, b)`; padding entries hold 0xFFFF and sort last.
 template <int TPC, class LessF>
