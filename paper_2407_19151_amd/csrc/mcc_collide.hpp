@@ -48,13 +48,13 @@ struct CellMem {
 // ---------------------------------------------------------------------------
 // Pair scatter (Sec. 3.1-3.2, Eq. (12)); non-relativistic
 // ---------------------------------------------------------------------------
-template <typename KR>
+template <typename KR, class Tab>
 __device__ __forceinline__ void scatter_pair_nr(double *vx, double *vy, double *vz,
                                                 const double *w, int I, int J, uint32_t kp,
                                                 double coef_f_nmin_dV, double fa, double fb,
                                                 int method, uint32_t cell, uint32_t step_lo,
                                                 uint32_t c3, uint32_t k0, uint32_t k1,
-                                                const double2 *n97tab) {
+                                                const Tab *n97tab) {
   using K = KMath<KR>;
   const double vix = vx[I], viy = vy[I], viz = vz[I];
   const double vjx = vx[J], vjy = vy[J], vjz = vz[J];
@@ -677,6 +677,15 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
   static_assert(!GL || TPC <= 512, "the global layout runs at most 8 waves per cell");
   static_assert(!TAN || (!REL && sizeof(KR) == 8 && LAY != LAYOUT_COMPACT && !DIAG),
                 "the tangent form is FP64 non-relativistic, without diagnostics");
+  // FP32 kinematics in the compact layout from 1024 particles up: the N97
+  // table in LDS as the FP32 values its uses take (room the smaller
+  // variants would pay for in resident cells)
+  constexpr bool TAB_LDS = sizeof(KR) == 4 && !REL && LAY == LAYOUT_COMPACT && CAP >= 1024;
+  __shared__ float2 s_tab[TAB_LDS ? N97_TN : 1];
+  if constexpr (TAB_LDS) {
+    for (int i = threadIdx.x; i < N97_TN; i += TPC)
+      s_tab[i] = make_float2((float)A.n97[i].x, (float)A.n97[i].y);
+  }
   __shared__ double red[2 * 6 * NW];
   uint64_t *redu = reinterpret_cast<uint64_t *>(red);
   __shared__ uint32_t wsum[NW];
@@ -1089,7 +1098,8 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
       const int Nmax = abig ? na : nb, Nmin = abig ? nb : na;
       const double nmin = intra ? (double)(na - 1) : (double)Nmin;
       // N_min / dV of each collision of the pass (once per pass, not per chain)
-      const double nmin_dv = nmin / dV, nmin_dv_b = (double)(nb - 1) / dV;
+      // (scalar: a per-lane select would pull the division into the chain loop)
+      const double nmin_dv = uni(nmin / dV), nmin_dv_b = uni((double)(nb - 1) / dV);
       const bool odd = intra && (na & 1);
       if constexpr (NXN) {
         // N x N (Sec. 3.1): every pair once with s of Eq. (10)
@@ -1130,6 +1140,9 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             else if constexpr (sizeof(KR) == 8)
               scatter_pair_nr_f64(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, C.fa, C.fb, A.method,
                                   (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
+            else if constexpr (TAB_LDS)
+              scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, C.fa, C.fb, A.method,
+                                  (uint32_t)cell, step_lo, c3p, k0, k1, s_tab);
             else
               scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, C.fa, C.fb, A.method,
                                   (uint32_t)cell, step_lo, c3p, k0, k1, A.n97);
@@ -1152,11 +1165,14 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
         const bool oddb = dual && (nb & 1);
         const int nchb = dual ? (oddb ? 1 + (nb - 3) / 2 : nb / 2) : 0;
         const uint32_t c3pb = ctr3(step, k + 1, PURPOSE_PAIR);
+        // inter: N_max = q N_min + rem, so chain ch holds q + (ch < rem) pairs
+        const int q_int = (!intra && Nmin > 0) ? uni(Nmax / Nmin) : 0;
+        const int rem_int = Nmax - q_int * Nmin;
         for (int ch0 = t; ch0 < ncha + nchb; ch0 += TPC) {
           const bool sb = ch0 >= ncha;  // (dual pass) a chain of species b
           const int ch = sb ? ch0 - ncha : ch0;
           const bool odds = sb ? oddb : odd;
-          const int len = intra ? ((odds && ch == 0) ? 3 : 1) : (Nmax - ch + Nmin - 1) / Nmin;
+          const int len = intra ? ((odds && ch == 0) ? 3 : 1) : q_int + (ch < rem_int ? 1 : 0);
           // the constants of the collision this chain belongs to
           const CollConst &Cs = s_cc[sb ? 1 : 0];
           const double nmins_dv = sb ? nmin_dv_b : nmin_dv;
@@ -1205,6 +1221,9 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
             else if constexpr (sizeof(KR) == 8)
               scatter_pair_nr_f64(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, Cs.fa, Cs.fb, A.method,
                                   (uint32_t)cell, step_lo, c3s, k0, k1, A.n97);
+            else if constexpr (TAB_LDS)
+              scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, Cs.fa, Cs.fb, A.method,
+                                  (uint32_t)cell, step_lo, c3s, k0, k1, s_tab);
             else
               scatter_pair_nr<KR>(M.vx, M.vy, M.vz, M.w, I, J, kp, cf, Cs.fa, Cs.fb, A.method,
                                   (uint32_t)cell, step_lo, c3s, k0, k1, A.n97);
@@ -1267,11 +1286,14 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
           for_owned<TPC, PPT, !GL>(n, mom);
         }
         MCC_PHASE(10);  // momentum reduction
+        // (no closing barrier: the energy reduction below writes the other
+        // part of `red`, and its own barrier orders these reads before any
+        // later write; the tangent form's energy sums need all of `red`)
         double tot[6];
         if (dual)
-          block_sum<TPC, 6>(P, red, tot);
+          block_sum<TPC, 6, TAN>(P, red, tot);
         else
-          block_sum<TPC, NP>(P, red, tot);
+          block_sum<TPC, NP, TAN>(P, red, tot);
         const double D = ma * s_sw2[a] + (intra ? 0.0 : mb * s_sw2[b]);
         Bx = tot[0] / D;
         By = tot[1] / D;
@@ -1370,6 +1392,9 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
           });
         }
         MCC_PHASE(12);  // energy reduction
+        // the part of `red` the momentum reduction left alone; no closing
+        // barrier unless the diagnostics reuse all of `red` next
+        double *ered = red + 6 * NW;
         dEs1 = 0.0;
         if constexpr (TAN) {
           double tot[NE];
@@ -1389,17 +1414,17 @@ __global__ void __launch_bounds__(TPC, min_waves(TPC, CAP, LAY, sizeof(KR) == 8,
           }
         } else if (dual) {
           // two intra-species violations, each corrected on its own species
-          block_sum_c2<TPC>(es, ec, es1, ec1, red, dEs0, dEs1);
+          block_sum_c2<TPC, DIAG>(es, ec, es1, ec1, ered, dEs0, dEs1);
         } else if (intra) {
           CSum<1> Cv;
           Cv.s[0] = es;
           Cv.c[0] = ec;
           double out[1];
-          block_csum<TPC, 1>(Cv, red, out);
+          block_csum<TPC, 1, false, DIAG>(Cv, ered, out);
           dEs0 = out[0];
         } else {
           double tot[2];
-          block_sum_c1<TPC, 2>(es, ec, Ev, red, dEs0, tot);
+          block_sum_c1<TPC, 2, DIAG>(es, ec, Ev, ered, dEs0, tot);
           if (dEs0 != 0.0) {
             const double dE = dEs0;
             const double ea = s_sw[a] / na * tot[0], eb = s_sw[b] / nb * tot[1];

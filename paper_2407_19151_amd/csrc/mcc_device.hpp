@@ -249,8 +249,9 @@ struct CSum {
 
 // Sum of N compensated values over the block; every thread receives the
 // totals.  `red` is LDS scratch of at least 2*N*(TPC/64) doubles.  Ends with a
-// barrier so `red` may be reused right after.
-template <int TPC, int N, bool G = false>
+// barrier so `red` may be reused right after (with TAIL; without it, `red`
+// must not be written again before the workgroup's next barrier).
+template <int TPC, int N, bool G = false, bool TAIL = true>
 __device__ __forceinline__ void block_csum(CSum<N> &v, double *red, double out[N]) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = threadIdx.x / WAVE;
@@ -282,13 +283,14 @@ __device__ __forceinline__ void block_csum(CSum<N> &v, double *red, double out[N
     }
     out[i] = s + c;
   }
-  __syncthreads();
+  if constexpr (TAIL) __syncthreads();
 }
 
 // Plain FP64 sum of N values over the block; every thread receives the same
 // totals (the xor butterfly adds the same two operands on both partners).
-// `red` is LDS scratch of at least N*(TPC/64) doubles.  Ends with a barrier.
-template <int TPC, int N>
+// `red` is LDS scratch of at least N*(TPC/64) doubles.  Ends with a barrier
+// (without TAIL, `red` must not be written again before the next barrier).
+template <int TPC, int N, bool TAIL = true>
 __device__ __forceinline__ void block_sum(double v[N], double *red, double out[N]) {
   const int lane = threadIdx.x & (WAVE - 1);
   const int wid = threadIdx.x / WAVE;
@@ -311,13 +313,13 @@ __device__ __forceinline__ void block_sum(double v[N], double *red, double out[N
     for (int w = 1; w < NW; ++w) acc += red[w * N + i];
     out[i] = acc;
   }
-  __syncthreads();
+  if constexpr (TAIL) __syncthreads();
 }
 
 // One compensated value (s, c) and N plain values summed over the block in
 // one pass; every thread receives the totals.  `red` holds at least
-// (N+2)*(TPC/64) doubles.  Ends with a barrier.
-template <int TPC, int N>
+// (N+2)*(TPC/64) doubles.  Ends with a barrier (as block_sum with TAIL).
+template <int TPC, int N, bool TAIL = true>
 __device__ __forceinline__ void block_sum_c1(double &s, double &c, double v[N], double *red,
                                              double &out_c, double out[N]) {
   const int lane = threadIdx.x & (WAVE - 1);
@@ -354,14 +356,14 @@ __device__ __forceinline__ void block_sum_c1(double &s, double &c, double v[N], 
     for (int w = 1; w < NW; ++w) acc += red[w * M + 2 + i];
     out[i] = acc;
   }
-  __syncthreads();
+  if constexpr (TAIL) __syncthreads();
 }
 
 // Two compensated values summed over the block in one pass, each exactly as
 // block_sum_c1 sums its one (same butterfly, same order across waves);
 // every thread receives both totals.  `red` holds at least 4*(TPC/64)
-// doubles.  Ends with a barrier.
-template <int TPC>
+// doubles.  Ends with a barrier (as block_sum with TAIL).
+template <int TPC, bool TAIL = true>
 __device__ __forceinline__ void block_sum_c2(double &s0, double &c0, double &s1, double &c1,
                                              double *red, double &out0, double &out1) {
   const int lane = threadIdx.x & (WAVE - 1);
@@ -394,7 +396,7 @@ __device__ __forceinline__ void block_sum_c2(double &s0, double &c0, double &s1,
   }
   out0 = ss0 + cc0;
   out1 = ss1 + cc1;
-  __syncthreads();
+  if constexpr (TAIL) __syncthreads();
 }
 
 // min and max of N u64 values over the block (all threads receive them)
@@ -847,8 +849,10 @@ __device__ __forceinline__ double n97_newton(double s, double A) {
   return A - g / dL;
 }
 
-template <typename T>
-__device__ __forceinline__ T n97_A_fast(T s, const double2 *tab) {
+// (tab: double2 in HBM, or float2 holding the same entries rounded to FP32,
+// which is what the FP32 form takes of them)
+template <typename T, class Tab>
+__device__ __forceinline__ T n97_A_fast(T s, const Tab *tab) {
   using M = KMath<T>;
   if (!(s > T(0))) return T(__builtin_inf());
   if (s > M::S_ISO) return T(0);
@@ -858,7 +862,7 @@ __device__ __forceinline__ T n97_A_fast(T s, const double2 *tab) {
   int i = (int)x;
   i = i < 0 ? 0 : (i > N97_TN - 2 ? N97_TN - 2 : i);
   const T f = x - T(i);
-  const double2 k0 = tab[i], k1 = tab[i + 1];
+  const Tab k0 = tab[i], k1 = tab[i + 1];
   const T f2 = f * f, f3 = f2 * f;
   // Hermite basis; the table holds A and h dA/dt at the knots
   const T A = (T(2) * f3 - T(3) * f2 + T(1)) * T(k0.x) + (f3 - T(2) * f2 + f) * T(k0.y) +
@@ -870,9 +874,9 @@ __device__ __forceinline__ T n97_A_fast(T s, const double2 *tab) {
 }
 
 // Sampled polar angle: oc = 1 - cos(theta), st = sin(theta).
-template <typename T>
+template <typename T, class Tab>
 __device__ __forceinline__ void sample_angle(int method, T s, uint32_t a0, uint32_t a1, T &oc,
-                                             T &st, const double2 *n97tab) {
+                                             T &st, const Tab *n97tab) {
   using M = KMath<T>;
   const T u0 = M::u(a0);
   if (method == 0) {  // TA77: tan(theta/2) ~ N(0, s/2)
