@@ -144,3 +144,30 @@ def test_fp32_kinematics_large_cells_match_the_oracle(ctx):
         print("  fp32 against the oracle: %s" % info, flush=True)
         for k in ("pairs", "collisions", "failed"):
             assert sg[k] == so[k]
+
+
+def test_fp32_lds_table_gives_the_bits_of_the_hbm_table(ctx):
+    """The FP32 compact variants from 1024 particles up read Nanbu's A(s)
+    table from an LDS copy held as FP32 values; the smaller ones read the
+    FP64 table from HBM and round each entry where they use it.  The 256x1024
+    and 256x512 variants (same threads per cell, both compact) on cells of
+    257-512 particles, N97 over several steps, must give the same bits."""
+    from paper_2407_19151_amd import native, runner
+    from gpu_helpers import custom_workload
+    sizes = [(200, 100), (180, 170), (300, 211), (256, 256), (129, 130), (40, 30)]
+    wl = custom_workload(sizes, seed=63, weight_mode="lognormal")
+    out = []
+    for variant in (4, 5):  # 256x512 (table in HBM), 256x1024 (table in LDS)
+        print("fp32 table check, variant %d" % variant, flush=True)
+        dw = runner.DeviceWorkload(wl)
+        try:
+            ctx.set_variant(2, variant)
+            for step in range(4):
+                runner.collide_sorted(ctx, dw, step, params=runner.params_for(
+                    wl, precision=native.MCC_FP32_KINEMATICS))
+            out.append(dw.velocities())
+        finally:
+            ctx.set_variant(2, -1)
+        assert ctx.device_error() == 0
+    assert np.array_equal(out[0], out[1])
+    assert not np.array_equal(out[0], wl.velocities())
