@@ -175,7 +175,9 @@ mcc_status mcc_device_error(mcc_ctx *ctx, int32_t *code);
  * capacity) table: 0 (64,128), 1 (64,256), 2 (128,256), 3 (128,512),
  * 4 (256,512), 5 (256,1024), 6 (512,1024), 7 (512,2048), 8 (1024,2048),
  * 9 (1024,4096), 10 (64,32768, one wave with global scratch), 11 (256,2048),
- * 12 (512,4096), 13 (256,4096).  In relativistic mode 9, 12 and 13 run in
+ * 12 (512,4096), 13 (256,4096), 14 (256,32768) and 15 (512,32768) (four and
+ * eight waves with global scratch; the diagnostic and tangent forms run them
+ * as 10).  In relativistic mode 9, 12 and 13 run in
  * global scratch: as (256,4096), four waves, in the order-N step, and as
  * (64,4096), one wave, in its diagnostic, N x N and duplicity forms.  -1 restores the default, which depends on
  * the precision mode (built-in table, the fastest measured on lognormal
